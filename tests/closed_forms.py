@@ -1,0 +1,94 @@
+"""Closed forms for the interaction counts and values of the arithmetic rule
+system, derived by hand from the rule texts (independent of both evaluators).
+
+Notation: a numeral S^k Z has value k.  Add(y,r) = x consumes x one S per
+step: Add><S a times, then Add><Z once.  Mul(y,r) = x with x = S^a Z,
+y = S^b Z fires Mul><S a times (each spawning a Dup of y and an Add of one
+copy), the Dups copy b S's and one Z each, the Adds consume b S's each, the
+final Mul><Z erases the last copy of y through b Era><S and one Era><Z.
+Fib(r) = S^n Z computes fib(n) with fib(0) = fib(1) = 1.
+"""
+from __future__ import annotations
+
+from functools import lru_cache
+
+
+def add_count(a: int, b: int) -> int:
+    return a + 1
+
+
+def mul_count(a: int, b: int) -> int:
+    return 2 * a * b + 3 * a + b + 2
+
+
+def mul_per_rule(a: int, b: int) -> dict:
+    return {"Add><S": a * b, "Add><Z": a, "Mul><S": a, "Mul><Z": 1, "Dup><S": a * b,
+            "Dup><Z": a, "Era><S": b, "Era><Z": 1, "Fib><Z": 0, "Fib><S": 0,
+            "Fib2><Z": 0, "Fib2><S": 0}
+
+
+def fib_value(n: int) -> int:
+    a, b = 1, 1  # fib(0), fib(1)
+    for _ in range(n):
+        a, b = b, a + b
+    return a
+
+
+@lru_cache(maxsize=None)
+def fib_count(n: int) -> int:
+    """T(0) = 1 (Fib><Z), T(1) = 2 (Fib><S, Fib2><Z); for n >= 2 Fib><S and
+    Fib2><S (2), the Dup of S^(n-2) Z (n-1), then Fib(n-2) and Fib(n-1) and
+    the Add consuming fib(n-2) (fib(n-2)+1)."""
+    if n == 0:
+        return 1
+    if n == 1:
+        return 2
+    return fib_count(n - 1) + fib_count(n - 2) + fib_value(n - 2) + n + 2
+
+
+def tree_count(values) -> int:
+    """Balanced Add tree, left operand principal: every internal node costs
+    (sum of its left subtree) + 1."""
+    values = list(values)
+    total = 0
+    level = values
+    while len(level) > 1:
+        nxt = []
+        for i in range(0, len(level), 2):
+            total += level[i] + 1
+            nxt.append(level[i] + level[i + 1])
+        level = nxt
+    return total
+
+
+def expr_value(e) -> int:
+    if e[0] == "num":
+        return e[1]
+    if e[0] == "add":
+        return expr_value(e[1]) + expr_value(e[2])
+    if e[0] == "mul":
+        return expr_value(e[1]) * expr_value(e[2])
+    return fib_value(expr_value(e[1]))
+
+
+def expr_count(e) -> int:
+    if e[0] == "num":
+        return 0
+    if e[0] == "fib":
+        return expr_count(e[1]) + fib_count(expr_value(e[1]))
+    c = expr_count(e[1]) + expr_count(e[2])
+    v1, v2 = expr_value(e[1]), expr_value(e[2])
+    if e[0] == "add":
+        return c + add_count(v1, v2)
+    return c + mul_count(v1, v2)
+
+
+# number of agents in each rule's right-hand side (count of upper-case symbols
+# in the rule text after the arrow), in ARITH_RULE_TEXTS order
+def rhs_agent_counts(rule_texts) -> list:
+    import re
+    out = []
+    for t in rule_texts:
+        rhs = t.split("->", 1)[1]
+        out.append(len(re.findall(r"\b[A-Z][A-Za-z0-9]*", rhs)))
+    return out
