@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark: interactions/s of the MI355X interaction-net evaluator.
+
+A step is one pass of the whole hot path over one batch of synthetic input:
+restore the loaded nets (device to device), reduce every net to normal form
+(int/com step loop, pointer jumping), with the inputs resident in HBM.
+
+Default workload: 4096 independent nets (Add trees, Mul, Fib; lognormal sizes,
+seed 0) reduced by one persistent launch.  --workload mul|fib|addtree times a
+single net instead.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "interactions/sec (single net vs batched/served) + p50/p99 net latency, 1 MI355X"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def size_batch(P, R, net_list, wg):
+    """Find exact heap needs (agents and name cells are deterministic: they
+    depend only on the per-rule counts) by reducing once with growing caps."""
+    n = len(net_list)
+    acap = np.array([max(1024, 16 * x.n_agents + 4096) for x in net_list], dtype=np.int64)
+    ncap = 4 * acap
+    used_a = np.zeros(n, np.int64)
+    used_n = np.zeros(n, np.int64)
+    steps = np.zeros(n, np.int64)
+    inter = np.zeros(n, np.int64)
+    pending = list(range(n))
+    for _ in range(8):
+        if not pending:
+            break
+        h = P.batch_load(R, [net_list[i] for i in pending], agent_caps=acap[pending],
+                         name_caps=ncap[pending])
+        h.set_config(wg_size=wg)
+        rs = h.reduce()
+        h.free()
+        again = []
+        for j, i in enumerate(pending):
+            r = rs[j]
+            if r.status == P.ENOMEM:
+                acap[i] *= 8
+                ncap[i] *= 8
+                again.append(i)
+            elif r.status in (P.OK, P.STUCK):
+                used_a[i], used_n[i] = r.agents_used, r.names_used
+                steps[i], inter[i] = r.steps, r.interactions
+            else:
+                raise RuntimeError(f"net {i}: status {r.status}")
+        pending = again
+    if pending:
+        raise RuntimeError(f"{len(pending)} nets did not fit")
+    return used_a, used_n, steps, inter
+
+
+def cpu_baseline(R, net_list, seconds):
+    import oracle
+    t0 = time.perf_counter()
+    tot = 0
+    k = 0
+    while k < len(net_list) and time.perf_counter() - t0 < seconds:
+        r = oracle.reduce(R, net_list[k])
+        tot += r.interactions
+        k += 1
+    dt = time.perf_counter() - t0
+    return {"value": tot / dt, "unit": "interactions/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {k} of {len(net_list)} nets in launch order, {tot} interactions, "
+                      f"{dt:.1f} s, single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="batch", choices=["batch", "mul", "fib", "addtree"])
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--n-nets", type=int, default=4096)
+    ap.add_argument("--fib-n", type=int, default=27)
+    ap.add_argument("--wg", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-single", action="store_true", help="skip the single-net side measurement")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(nets are independent; see DESIGN.md for how the batch would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1404_0076_amd as P
+    from paper_1404_0076_amd import nets
+
+    torch.cuda.set_device(0)
+    R = nets.arith_rules()
+    if args.workload == "batch":
+        net_list = nets.config4_batch(seed=args.seed, n_nets=args.n_nets)
+        workload = {"workload": f"batch of {args.n_nets} nets (Add tree / Mul / Fib mix, "
+                                f"lognormal sizes median 2e3 interactions, seed {args.seed})",
+                    "n_nets": args.n_nets, "seed": args.seed}
+    elif args.workload == "mul":
+        net_list = [nets.config2_mul(args.seed)]
+        m = net_list[0].meta
+        workload = {"workload": f"single net Mul(S^{m['a']} Z, S^{m['b']} Z), seed {args.seed}"}
+    elif args.workload == "fib":
+        net_list = [nets.config3_fib(args.fib_n)]
+        workload = {"workload": f"single net Fib(S^{args.fib_n} Z)"}
+    else:
+        net_list = [nets.config1_add_tree(args.seed)]
+        workload = {"workload": f"single net: balanced Add tree over 1024 numerals in [0,256), "
+                                f"seed {args.seed}"}
+    wg = args.wg or (256 if len(net_list) > 1 else 1024)
+    log(f"sizing {len(net_list)} nets (wg {wg})")
+    used_a, used_n, steps, inter = size_batch(P, R, net_list, wg)
+    order = np.argsort(-steps, kind="stable").astype(np.int32)  # longest critical path first
+    h = P.batch_load(R, net_list, agent_caps=used_a + 64, name_caps=used_n + 64)
+    h.set_config(wg_size=wg)
+    h.set_order(order)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        h.reset()
+        h.reduce_async()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        h.reset()
+        ev[k][1].record(stream)
+        h.reduce_async()
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rs = h.results()
+    bad = [i for i, r in enumerate(rs) if r.status not in (P.OK, P.STUCK)]
+    if bad:
+        raise RuntimeError(f"{len(bad)} nets failed, e.g. net {bad[0]} status {rs[bad[0]].status}")
+    total = int(sum(r.interactions for r in rs))
+    assert total == int(inter.sum()), "interaction count changed between runs"
+    kern_ms = np.array([ev[k][1].elapsed_time(ev[k][2]) for k in range(args.steps)])
+    reset_ms = np.array([ev[k][0].elapsed_time(ev[k][1]) for k in range(args.steps)])
+    ms_per_step = wall * 1000.0 / args.steps
+    value = total * args.steps / wall
+    # algorithmic bytes: per-rule counts x bytes per interaction of each rule
+    rb = h.rule_bytes().astype(np.float64)
+    alg = 0.0
+    for i in range(len(net_list)):
+        alg += float(np.dot(h.per_rule(i).astype(np.float64), rb))
+    kmean = float(kern_ms.mean())
+    achieved = alg / (kmean * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": value, "unit": "interactions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic", "config": dict(workload, wg_size=wg,
+                                            interactions_per_step=total),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_reduce", "kernel_ms": kmean,
+                     "algorithmic_bytes": alg},
+        "reset_ms": float(reset_ms.mean()),
+        "max_steps_per_net": int(steps.max()),
+    }
+    h.free()
+    if args.workload == "batch" and not args.no_single:
+        # the plain single-net evaluator on the same GPU, for the comparison
+        single = nets.config2_mul(args.seed)
+        ua, un, st, it = size_batch(P, R, [single], 1024)
+        hs = P.batch_load(R, [single], agent_caps=ua + 64, name_caps=un + 64)
+        hs.set_config(wg_size=1024)
+        hs.reset(); hs.reduce_async(); torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(3):
+            hs.reset()
+            hs.reduce_async()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / 3
+        out["single_net"] = {"workload": f"Mul(S^{single.meta['a']} Z, S^{single.meta['b']} Z)",
+                             "value": float(it[0]) / dt, "ms": dt * 1000, "steps": int(st[0])}
+        hs.free()
+    if not args.no_cpu_baseline:
+        ordered = [net_list[i] for i in order] if args.workload == "batch" else net_list
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(R, ordered, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

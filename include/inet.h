@@ -1,0 +1,211 @@
+/*
+ * inet.h -- C ABI of the MI355X evaluator for the lightweight interaction
+ * calculus (Jiresch, "Towards a GPU-based implementation of interaction nets").
+ *
+ * The library reduces nets to normal form on one GPU.  The hot path is the
+ * repeated parallel step of Section 3 (evaluate() in Section 3.6): apply the
+ * rule of every active pair (int, Section 3.4), then resolve the name
+ * equations that the right-hand sides produced (com, Section 3.5), until no
+ * active pair remains.  sub and col are deferred to the read-back (Theorem 1,
+ * Section 2.2).  All arithmetic is exact int32/uint64: results are bit-exact.
+ *
+ * ------------------------------------------------------------------------
+ * Input format (host int32 arrays; the caller keeps ownership, every call
+ * copies what it needs before returning).
+ *
+ *   term ref r:  r >= 0  agent r of the same net
+ *                r <  0  name (-1 - r), a name id in [0, n_names)
+ *   label[n_agents]       symbol of each agent, in [0, rules->n_symbols)
+ *   port[n_agents][2]     refs on the auxiliary ports (entries at or past
+ *                         the agent's arity are ignored).  An agent ref in a
+ *                         port attaches that agent's principal port there,
+ *                         i.e. the nested term alpha(.., beta(..), ..).
+ *   eq_lhs[n_eqs], eq_rhs[n_eqs]   the multiset Delta of equations t = s
+ *   A net is a configuration <t | Delta> (Section 2.2): every agent must be
+ *   attached exactly once and below some equation side (finite terms), every
+ *   name occurs at most twice in Delta; the names occurring once form the
+ *   interface t, ordered by ascending id.
+ *
+ * Rule format (inet_rules): the rule alpha(x) = beta(y) -> Theta of Section
+ * 2.2.  rule_lhs[k] = {alpha, beta}; rhs[rhs_off[k] .. rhs_off[k+1]) holds
+ * n_eq followed by the n_eq equations of Theta, each side a prefix-encoded
+ * term (a label >= 0 followed by its arity subterms, or a name -1-v).  Inside
+ * a rule, names 0..ar(alpha)-1 are alpha's auxiliary ports, the next
+ * ar(beta) names are beta's; each of these occurs exactly once in Theta, every
+ * other name exactly twice (bound names, renamed apart at every use).  At most
+ * one rule per unordered pair {alpha, beta}; alpha != beta; arity <= 2;
+ * n_symbols <= INET_MAX_SYMBOLS; n_rules <= INET_MAX_RULES; after the library
+ * folds the internal com/sub steps of Theta, a rule may create at most
+ * INET_MAX_RHS_AGENTS agents, INET_MAX_RHS_EQS links and INET_MAX_RHS_FRESH
+ * fresh names.
+ *
+ * Output: the canonical normal-form stream (inet_readback)
+ *   [n_iface] T(iface_0) .. T(iface_n-1) [n_res] T(l_0) T(r_0) ..
+ *   T(agent) = label followed by T of its auxiliary ports in order;
+ *   T(name)  = -(1 + c), c numbered by first appearance in the stream.
+ *   The residual equations are the active pairs that have no rule, each
+ *   oriented so that its name-erased encoding is the smaller one first, and
+ *   sorted by those encodings.  Closed loops x = x are dropped; a name cycle
+ *   with no agent and no interface name (a vicious circle) is not part of the
+ *   stream.
+ *
+ * Device memory: every handle lives in ONE caller-provided device buffer
+ * (e.g. a torch uint8 tensor); size it with inet_workspace_bytes.  The
+ * library never allocates device memory itself except a small pinned host
+ * staging area; the buffer must outlive the handle.
+ *
+ * Streams: the *_async entry points enqueue work on the caller's stream and
+ * return at once; inet_results synchronises that stream.  A handle is not
+ * thread-safe; calls on one handle must not overlap.
+ *
+ * Errors: every function returns an inet_status; no exception crosses the
+ * ABI.  inet_strerror gives a static message.
+ */
+#ifndef INET_H
+#define INET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  INET_MAX_ARITY = 2,
+  INET_MAX_SYMBOLS = 64,
+  INET_MAX_RULES = 64,
+  INET_MAX_RHS_AGENTS = 8,
+  INET_MAX_RHS_EQS = 8,
+  INET_MAX_RHS_FRESH = 8
+};
+
+typedef enum {
+  INET_OK = 0,
+  INET_STUCK = 1,    /* reduced; some active pair had no rule (a residual) */
+  INET_EINVAL = -1,  /* malformed rules, net, argument or configuration     */
+  INET_ENOMEM = -2,  /* agent/name/queue capacity or workspace too small;
+                        the net's state is then unusable (reload it)        */
+  INET_ELIMIT = -3,  /* max_steps reached before normal form; resumable     */
+  INET_ERANGE = -4,  /* output buffer too small; *len holds the need        */
+  INET_EAGAIN = -5,  /* server: no free slot or memory; retry later         */
+  INET_EHIP = -6,    /* a HIP runtime call failed                            */
+  INET_ENOSYS = -7,  /* not supported on this device / build                */
+  INET_EINTERNAL = -8 /* an invariant of the evaluator was violated          */
+} inet_status;
+
+typedef struct {
+  int32_t n_symbols;
+  const int32_t *arity;     /* [n_symbols], each 0..2                       */
+  int32_t n_rules;
+  const int32_t *rule_lhs;  /* [n_rules][2]                                 */
+  const int32_t *rhs_off;   /* [n_rules + 1]                                */
+  const int32_t *rhs;       /* [rhs_off[n_rules]]                           */
+} inet_rules;
+
+typedef struct {
+  int32_t status;           /* inet_status of this net                     */
+  int32_t n_stuck;          /* residual active pairs without a rule        */
+  uint64_t interactions;    /* int steps applied (order independent)       */
+  uint64_t steps;           /* parallel steps run (schedule dependent)     */
+  int64_t agents_used;      /* agent slots in use (heap top)               */
+  int64_t names_used;       /* name cells in use                           */
+  int32_t max_frontier;     /* largest set of active pairs in one step     */
+  int32_t loops;            /* closed loops x = x dropped                   */
+} inet_result;
+
+/* Launch shape of the reduction kernel; 0 fields take the defaults. */
+typedef struct {
+  int32_t wg_size;          /* lanes per net engine: 64,128,256,512,1024   */
+  int32_t jump;             /* 1: compress name chains after the loop      */
+  int32_t max_resident;     /* cap on simultaneously resident net engines  */
+} inet_config;
+
+typedef struct inet_net inet_net;
+
+/* Workspace bytes for n_nets nets.  agent_cap[i] / name_cap[i]: capacity of
+ * net i's agent heap and name cells (>= its initial size; 0 = a default of 4x
+ * the initial size plus 1024).  n_eqs[i], n_agents[i], n_names[i]: initial
+ * sizes. */
+int inet_workspace_bytes(const inet_rules *rules, int32_t n_nets, const int64_t *n_agents,
+                         const int64_t *n_eqs, const int32_t *n_names, const int64_t *agent_cap,
+                         const int64_t *name_cap, size_t *bytes);
+
+/* Load one net (Section 2.2 configuration) and validate it (A1 of the hot
+ * path).  dev/dev_bytes: the caller's device buffer (see above).  The upload
+ * is enqueued on stream; on return the host arrays may be released. */
+int inet_load(const inet_rules *rules, const int32_t *label, const int32_t *port,
+              int32_t n_agents, const int32_t *eq_lhs, const int32_t *eq_rhs, int32_t n_eqs,
+              int32_t n_names, int64_t agent_cap, int64_t name_cap, void *dev, size_t dev_bytes,
+              hipStream_t stream, inet_net **out);
+
+/* Load n_nets independent nets packed back to back: net i owns agents
+ * [agent_off[i], agent_off[i+1]) and equations [eq_off[i], eq_off[i+1]) of the
+ * packed arrays; refs inside a net are local to that net (agent r of net i is
+ * packed row agent_off[i] + r).  agent_cap/name_cap as for
+ * inet_workspace_bytes (may be NULL for defaults). */
+int inet_batch_load(const inet_rules *rules, int32_t n_nets, const int32_t *label,
+                    const int32_t *port, const int64_t *agent_off, const int32_t *eq_lhs,
+                    const int32_t *eq_rhs, const int64_t *eq_off, const int32_t *n_names,
+                    const int64_t *agent_cap, const int64_t *name_cap, void *dev,
+                    size_t dev_bytes, hipStream_t stream, inet_net **out);
+
+int inet_set_config(inet_net *h, const inet_config *cfg);
+int inet_get_config(const inet_net *h, inet_config *cfg);
+
+/* Order in which the persistent kernel hands nets to workgroups: a
+ * permutation of [0, n_nets) (longest-running nets first balances a batch). */
+int inet_set_order(inet_net *h, const int32_t *order);
+
+/* Reduce every net of the handle to normal form (or until max_steps parallel
+ * steps, 0 = no limit) with one persistent kernel launch on stream, then
+ * compress name chains (pointer jumping).  Enqueue only; resumable after
+ * INET_ELIMIT. */
+int inet_reduce_async(inet_net *h, hipStream_t stream, uint64_t max_steps);
+
+/* Synchronise stream and copy per-net results into out[n_nets]. */
+int inet_results(inet_net *h, hipStream_t stream, inet_result *out);
+
+/* inet_reduce_async + inet_results; returns the first net's status for a
+ * single net, else INET_OK if all nets ended OK/STUCK, else the first error. */
+int inet_reduce(inet_net *h, hipStream_t stream, uint64_t max_steps, inet_result *out);
+
+/* Restore every net to its loaded state (device to device, on stream). */
+int inet_reset(inet_net *h, hipStream_t stream);
+
+/* Canonical normal-form stream of net i (the sub* col* read-back of Theorem
+ * 1, Section 2.2).  Needs inet_results first.  cap too small: INET_ERANGE
+ * with *len set to the required words. */
+int inet_readback(inet_net *h, int32_t net, int32_t *buf, int64_t cap, int64_t *len);
+
+/* Per-rule interaction counts of net i (cap >= n_rules words). */
+int inet_per_rule(inet_net *h, int32_t net, uint64_t *counts, int32_t cap);
+
+/* Algorithmic bytes one interaction of each rule moves in the evaluator's
+ * layout (cap >= n_rules words): 8 (the pair) + 4 (label + ports) of both
+ * agents + 4 (label + ports) of each new agent + 4 per fresh name cell + 8 per
+ * link equation (a name-cell exchange or a frontier append). */
+int inet_rule_bytes(const inet_net *h, int32_t *bytes, int32_t cap);
+
+/* Host only (no device needed): validate and compile a rule table and report,
+ * per rule, the agents it creates, the fresh name cells (wires) and link
+ * equations left after folding the internal com/sub steps of its right-hand
+ * side, and its algorithmic bytes (as inet_rule_bytes).  Each output array
+ * may be NULL; otherwise it holds cap >= n_rules words. */
+int inet_rules_check(const inet_rules *rules, int32_t *n_new, int32_t *n_fresh, int32_t *n_links,
+                     int32_t *bytes, int32_t cap);
+
+int32_t inet_num_nets(const inet_net *h);
+void inet_free(inet_net *h);
+const char *inet_strerror(int status);
+
+/* Kernel time of the last reduction launch on this handle, measured with HIP
+ * events on the launch stream (ms); -1 if not available yet. */
+float inet_last_kernel_ms(inet_net *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,325 @@
+"""MI355X evaluator for the lightweight interaction calculus.
+
+Thin ctypes binding of ``libinet.so`` (C ABI in ``include/inet.h``): argument
+marshalling only.  Device memory and streams come from PyTorch; every step of
+the reduction runs in the library's HIP kernels.  There is no fallback: if the
+library is missing or no GPU is present, calls fail loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import nets  # noqa: F401  (re-exported for convenience)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libinet.so")
+
+OK, STUCK, EINVAL, ENOMEM, ELIMIT, ERANGE, EAGAIN, EHIP, ENOSYS, EINTERNAL = 0, 1, -1, -2, -3, -4, -5, -6, -7, -8
+
+EXPORTS = [
+    "inet_workspace_bytes", "inet_load", "inet_batch_load", "inet_set_config", "inet_get_config",
+    "inet_set_order", "inet_reduce_async", "inet_results", "inet_reduce", "inet_reset",
+    "inet_readback", "inet_per_rule", "inet_rule_bytes", "inet_num_nets", "inet_free",
+    "inet_strerror", "inet_last_kernel_ms", "inet_rules_check",
+]
+
+
+class InetError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {strerror(status)} ({status})")
+
+
+class _Rules(ctypes.Structure):
+    _fields_ = [("n_symbols", ctypes.c_int32), ("arity", ctypes.c_void_p),
+                ("n_rules", ctypes.c_int32), ("rule_lhs", ctypes.c_void_p),
+                ("rhs_off", ctypes.c_void_p), ("rhs", ctypes.c_void_p)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_stuck", ctypes.c_int32),
+                ("interactions", ctypes.c_uint64), ("steps", ctypes.c_uint64),
+                ("agents_used", ctypes.c_int64), ("names_used", ctypes.c_int64),
+                ("max_frontier", ctypes.c_int32), ("loops", ctypes.c_int32)]
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("wg_size", ctypes.c_int32), ("jump", ctypes.c_int32),
+                ("max_resident", ctypes.c_int32)]
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I32, _I64, _U64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+
+
+def library():
+    """Load libinet.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run paper_1404_0076_amd/build.py first")
+        lib = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "inet_workspace_bytes": [_P, _I32, _P, _P, _P, _P, _P, _P],
+            "inet_load": [_P, _P, _P, _I32, _P, _P, _I32, _I32, _I64, _I64, _P, ctypes.c_size_t, _P, _P],
+            "inet_batch_load": [_P, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P],
+            "inet_set_config": [_P, _P], "inet_get_config": [_P, _P], "inet_set_order": [_P, _P],
+            "inet_reduce_async": [_P, _P, _U64], "inet_results": [_P, _P, _P],
+            "inet_reduce": [_P, _P, _U64, _P], "inet_reset": [_P, _P],
+            "inet_readback": [_P, _I32, _P, _I64, _P], "inet_per_rule": [_P, _I32, _P, _I32],
+            "inet_rule_bytes": [_P, _P, _I32], "inet_num_nets": [_P],
+            "inet_rules_check": [_P, _P, _P, _P, _P, _I32],
+        }
+        for name, args in sig.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        lib.inet_free.argtypes = [_P]
+        lib.inet_free.restype = None
+        lib.inet_strerror.argtypes = [ctypes.c_int]
+        lib.inet_strerror.restype = ctypes.c_char_p
+        lib.inet_last_kernel_ms.argtypes = [_P]
+        lib.inet_last_kernel_ms.restype = ctypes.c_float
+        _lib = lib
+    return _lib
+
+
+def strerror(status: int) -> str:
+    return library().inet_strerror(int(status)).decode()
+
+
+def _arr(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    if a.size == 0:
+        a = np.zeros(1, dtype=dtype)
+    return a
+
+
+class RulesArg:
+    """Keeps the numpy arrays alive for the duration of a call."""
+
+    def __init__(self, rules):
+        self.arity = _arr(rules.arity_array(), np.int32)
+        self.lhs = _arr(rules.lhs, np.int32)
+        self.off = _arr(rules.rhs_off, np.int32)
+        self.rhs = _arr(rules.rhs, np.int32)
+        self.n_rules = rules.n_rules
+        self.s = _Rules(rules.sig.n_symbols, self.arity.ctypes.data, rules.n_rules,
+                        self.lhs.ctypes.data, self.off.ctypes.data, self.rhs.ctypes.data)
+
+    @property
+    def ptr(self):
+        return ctypes.byref(self.s)
+
+
+@dataclasses.dataclass
+class Result:
+    status: int
+    n_stuck: int
+    interactions: int
+    steps: int
+    agents_used: int
+    names_used: int
+    max_frontier: int
+    loops: int
+
+
+def workspace_bytes(rules, n_agents, n_eqs, n_names, agent_cap=None, name_cap=None) -> int:
+    R = RulesArg(rules)
+    n = len(n_agents)
+    na = _arr(n_agents, np.int64)
+    ne = _arr(n_eqs, np.int64)
+    nn = _arr(n_names, np.int32)
+    ac = _arr(agent_cap if agent_cap is not None else np.zeros(n), np.int64)
+    nc = _arr(name_cap if name_cap is not None else np.zeros(n), np.int64)
+    out = ctypes.c_size_t(0)
+    rc = library().inet_workspace_bytes(R.ptr, n, na.ctypes.data, ne.ctypes.data, nn.ctypes.data,
+                                        ac.ctypes.data, nc.ctypes.data, ctypes.byref(out))
+    if rc:
+        raise InetError(rc, "inet_workspace_bytes")
+    return int(out.value)
+
+
+def rules_check(rules) -> dict:
+    """Host-only compile of a rule table (inet_rules_check)."""
+    R = RulesArg(rules)
+    n = max(1, rules.n_rules)
+    out = {k: np.zeros(n, np.int32) for k in ("n_new", "n_fresh", "n_links", "bytes")}
+    rc = library().inet_rules_check(R.ptr, out["n_new"].ctypes.data, out["n_fresh"].ctypes.data,
+                                    out["n_links"].ctypes.data, out["bytes"].ctypes.data, n)
+    if rc:
+        raise InetError(rc, "inet_rules_check")
+    return {k: v[: rules.n_rules] for k, v in out.items()}
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream), stream
+
+
+class Handle:
+    """A loaded batch of nets (a single net is a batch of one)."""
+
+    def __init__(self, ptr, workspace, rules, n_nets):
+        self._h = ptr
+        self.workspace = workspace  # torch tensor that owns the device memory
+        self.rules = rules
+        self.n_nets = n_nets
+
+    def _check(self, rc, what):
+        if rc not in (OK, STUCK):
+            raise InetError(rc, what)
+        return rc
+
+    def set_config(self, wg_size: int = 0, jump: bool = True, max_resident: int = 0):
+        cfg = _Config(wg_size, 1 if jump else 0, max_resident)
+        self._check(library().inet_set_config(self._h, ctypes.byref(cfg)), "inet_set_config")
+
+    def get_config(self) -> dict:
+        cfg = _Config()
+        self._check(library().inet_get_config(self._h, ctypes.byref(cfg)), "inet_get_config")
+        return {"wg_size": cfg.wg_size, "jump": bool(cfg.jump), "max_resident": cfg.max_resident}
+
+    def set_order(self, order: Sequence[int]):
+        o = _arr(order, np.int32)
+        self._check(library().inet_set_order(self._h, o.ctypes.data), "inet_set_order")
+
+    def reduce_async(self, max_steps: int = 0, stream=None):
+        s, _ = _stream_handle(stream)
+        self._check(library().inet_reduce_async(self._h, s, max_steps), "inet_reduce_async")
+
+    def results(self, stream=None) -> List[Result]:
+        s, _ = _stream_handle(stream)
+        out = (_Result * self.n_nets)()
+        self._check(library().inet_results(self._h, s, out), "inet_results")
+        return [Result(r.status, r.n_stuck, r.interactions, r.steps, r.agents_used,
+                       r.names_used, r.max_frontier, r.loops) for r in out]
+
+    def reduce(self, max_steps: int = 0, stream=None) -> List[Result]:
+        s, _ = _stream_handle(stream)
+        out = (_Result * self.n_nets)()
+        rc = library().inet_reduce(self._h, s, max_steps, out)
+        if rc in (EINVAL, EHIP):
+            raise InetError(rc, "inet_reduce")
+        return [Result(r.status, r.n_stuck, r.interactions, r.steps, r.agents_used,
+                       r.names_used, r.max_frontier, r.loops) for r in out]
+
+    def reset(self, stream=None):
+        s, _ = _stream_handle(stream)
+        self._check(library().inet_reset(self._h, s), "inet_reset")
+
+    def readback(self, net: int = 0) -> np.ndarray:
+        n = ctypes.c_int64(0)
+        rc = library().inet_readback(self._h, net, None, 0, ctypes.byref(n))
+        if rc != ERANGE:
+            raise InetError(rc, "inet_readback")
+        buf = np.zeros(max(1, n.value), dtype=np.int32)
+        rc = library().inet_readback(self._h, net, buf.ctypes.data, buf.size, ctypes.byref(n))
+        self._check(rc, "inet_readback")
+        return buf[: n.value].copy()
+
+    def per_rule(self, net: int = 0) -> np.ndarray:
+        out = np.zeros(max(1, self.rules.n_rules), dtype=np.uint64)
+        self._check(library().inet_per_rule(self._h, net, out.ctypes.data, out.size), "inet_per_rule")
+        return out[: self.rules.n_rules]
+
+    def rule_bytes(self) -> np.ndarray:
+        out = np.zeros(max(1, self.rules.n_rules), dtype=np.int32)
+        self._check(library().inet_rule_bytes(self._h, out.ctypes.data, out.size), "inet_rule_bytes")
+        return out[: self.rules.n_rules]
+
+    def last_kernel_ms(self) -> float:
+        return float(library().inet_last_kernel_ms(self._h))
+
+    def free(self):
+        if self._h:
+            library().inet_free(self._h)
+            self._h = None
+            self.workspace = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def batch_load(rules, net_list: Sequence["nets.Net"], agent_caps=None, name_caps=None,
+               stream=None, device="cuda") -> Handle:
+    """Load independent nets into one handle (inet_batch_load)."""
+    import torch
+    label, port, a_off, eql, eqr, e_off, n_names = nets.pack(net_list)
+    n = len(net_list)
+    ac = _arr(agent_caps if agent_caps is not None else np.zeros(n), np.int64)
+    nc = _arr(name_caps if name_caps is not None else np.zeros(n), np.int64)
+    nbytes = workspace_bytes(rules, np.diff(a_off), np.diff(e_off), n_names, ac, nc)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    s, _ = _stream_handle(stream)
+    R = RulesArg(rules)
+    la, po, ao = _arr(label, np.int32), _arr(port, np.int32), _arr(a_off, np.int64)
+    el, er, eo, nn = _arr(eql, np.int32), _arr(eqr, np.int32), _arr(e_off, np.int64), _arr(n_names, np.int32)
+    h = ctypes.c_void_p()
+    rc = library().inet_batch_load(R.ptr, n, la.ctypes.data, po.ctypes.data, ao.ctypes.data,
+                                   el.ctypes.data, er.ctypes.data, eo.ctypes.data, nn.ctypes.data,
+                                   ac.ctypes.data, nc.ctypes.data, ctypes.c_void_p(ws.data_ptr()),
+                                   nbytes, s, ctypes.byref(h))
+    if rc:
+        raise InetError(rc, "inet_batch_load")
+    return Handle(h, ws, rules, n)
+
+
+def load(rules, net: "nets.Net", agent_cap: int = 0, name_cap: int = 0, stream=None,
+         device="cuda") -> Handle:
+    """Load one net (inet_load)."""
+    import torch
+    nbytes = workspace_bytes(rules, [net.n_agents], [net.n_eqs], [net.n_names], [agent_cap],
+                             [name_cap])
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    s, _ = _stream_handle(stream)
+    R = RulesArg(rules)
+    la, po = _arr(net.label, np.int32), _arr(net.port, np.int32)
+    el, er = _arr(net.eq_lhs, np.int32), _arr(net.eq_rhs, np.int32)
+    h = ctypes.c_void_p()
+    rc = library().inet_load(R.ptr, la.ctypes.data, po.ctypes.data, net.n_agents, el.ctypes.data,
+                             er.ctypes.data, net.n_eqs, net.n_names, agent_cap, name_cap,
+                             ctypes.c_void_p(ws.data_ptr()), nbytes, s, ctypes.byref(h))
+    if rc:
+        raise InetError(rc, "inet_load")
+    return Handle(h, ws, rules, 1)
+
+
+def reduce_net(rules, net, agent_cap: int = 0, name_cap: int = 0, wg_size: int = 0,
+               max_retries: int = 6, jump: bool = True):
+    """Load, reduce and read back one net; on ENOMEM reload with 4x capacity.
+    Returns (Result, normal-form stream, per-rule counts)."""
+    agent_cap = agent_cap or max(4 * net.n_agents + 4096, 1 << 16)
+    name_cap = name_cap or 4 * agent_cap
+    for _ in range(max_retries):
+        h = load(rules, net, agent_cap=agent_cap, name_cap=name_cap)
+        h.set_config(wg_size=wg_size, jump=jump)
+        res = h.reduce()[0]
+        if res.status == ENOMEM:
+            h.free()
+            agent_cap *= 4
+            name_cap *= 4
+            continue
+        nf = h.readback(0) if res.status in (OK, STUCK) else np.zeros(0, np.int32)
+        pr = h.per_rule(0)
+        h.free()
+        return res, nf, pr
+    raise InetError(ENOMEM, "reduce_net")
+
+
+def check_exports() -> List[str]:
+    """Names from include/inet.h missing in the library (empty when complete)."""
+    lib = library()
+    return [n for n in EXPORTS if not hasattr(lib, n)]

@@ -1,0 +1,91 @@
+// inet_internal.h -- device data layout shared by the host runtime and the
+// HIP kernels of the evaluator (not part of the public ABI).
+//
+// A net lives in its own region of the caller's device buffer:
+//   label[agent_cap], port0[agent_cap], port1[agent_cap]   agent heap (SoA int32)
+//   bind[name_cap]                                        one cell per name
+//   queue[2][qcap]    frontier double buffer: entries >= LDS capacity of the
+//                     running engine spill here; the saved frontier lives here
+//                     between launches; the initial equations start here
+//   stuck[scap]       active pairs without a rule
+//   per_rule[n_rules] uint64 interaction counts
+// A term ref is int32: r >= 0 agent slot, r < 0 name (-1 - r) = ~r.
+// A name cell holds EMPTY until one occurrence of the name has been extracted
+// to the top of an equation; it then holds the term on the other side of that
+// equation (the parked value); the second extraction takes the value and
+// forms the equation value = other (com).
+#ifndef INET_INTERNAL_H
+#define INET_INTERNAL_H
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace inet {
+
+constexpr int32_t EMPTY = 0x7fffffff;
+
+// compiled rule template (int32 words)
+constexpr int RT_WORDS = 48;
+constexpr int RT_NNEW = 0;    // agents created by the rule
+constexpr int RT_NALLOC = 1;  // agents needing a fresh slot (the first two reuse the pair's slots)
+constexpr int RT_NFRESH = 2;  // fresh name cells (wires between two new ports)
+constexpr int RT_NEQ = 3;     // link equations
+constexpr int RT_LABEL = 4;   // [8] labels of the new agents
+constexpr int RT_PORT = 12;   // [8][2] operands on the new agents' ports
+constexpr int RT_EQ = 28;     // [8][2] operands of the link equations
+constexpr int MAXNEW = 8, MAXEQ = 8, MAXFRESH = 8;
+
+// operand code: kind << 4 | index
+constexpr int OP_AUX = 0;    // index 0,1: first agent's ports; 2,3: second agent's ports
+constexpr int OP_NEW = 1;    // index k: new agent k
+constexpr int OP_FRESH = 2;  // index f: fresh name f
+constexpr int OP_NONE = 0xff;
+
+// net state, written by the kernels, read by the host (64 bytes)
+struct NetState {
+  unsigned long long interactions;
+  uint32_t steps;
+  int32_t status;
+  int32_t agent_top;
+  int32_t name_top;
+  int32_t frontier;      // entries of the saved frontier / initial equations
+  int32_t phase;         // 0: initial equations pending, 1: frontier saved, 2: done
+  int32_t parity;        // which queue buffer holds the saved frontier
+  int32_t n_stuck;
+  int32_t loops;
+  int32_t max_frontier;
+  int32_t pad[4];
+};
+
+enum { PHASE_INIT = 0, PHASE_RUN = 1, PHASE_DONE = 2 };
+
+// per-net descriptor (read-only for the kernels)
+struct NetDesc {
+  int32_t *label;
+  int32_t *port0;
+  int32_t *port1;
+  int32_t *bind;
+  int2 *queue0;
+  int2 *queue1;
+  int2 *stuck;
+  unsigned long long *per_rule;
+  NetState *st;
+  int32_t agent_cap;
+  int32_t name_cap;
+  int32_t qcap;
+  int32_t scap;
+  // initial image (for reset): offsets into the packed input copies
+  int64_t init_agent_off;
+  int64_t init_eq_off;
+  int32_t n_agents0;
+  int32_t n_eqs0;
+  int32_t n_names0;
+  int32_t order;  // position in the launch order (largest nets first)
+};
+
+// status codes as seen by the kernels (mirror inet_status)
+enum { ST_OK = 0, ST_STUCK = 1, ST_ENOMEM = -2, ST_ELIMIT = -3, ST_EINTERNAL = -8 };
+
+}  // namespace inet
+
+#endif

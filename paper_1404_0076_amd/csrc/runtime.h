@@ -1,0 +1,75 @@
+// runtime.h -- host-side structures of the evaluator (internal).
+#ifndef INET_RUNTIME_H
+#define INET_RUNTIME_H
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/inet.h"
+#include "inet_internal.h"
+
+namespace inet {
+
+struct CompiledRules {
+  int ns = 0, nr = 0;
+  std::vector<int32_t> arity;
+  std::vector<int32_t> rule_of;     // [ns*ns] 2*rule+swap or -1
+  std::vector<int32_t> templ;       // [nr*RT_WORDS]
+  std::vector<int32_t> blob;        // device image: rule_of | templ | arity
+  std::vector<int32_t> bytes;       // algorithmic bytes per interaction of each rule
+  std::vector<int32_t> rhs_agents;  // agents in each literal right-hand side
+};
+
+int compile_rules(const inet_rules *r, CompiledRules *out);
+
+// kernel launchers (kernels.hip)
+struct LaunchShape {
+  int wg;
+  int qcap;  // LDS frontier capacity per buffer
+};
+int launch_reset(const NetDesc *d_descs, int n_nets, const int32_t *init_label,
+                 const int32_t *init_port, const int32_t *init_eq, int nr, hipStream_t s);
+int launch_zero(int32_t *p, int n, hipStream_t s);
+int launch_reduce(const LaunchShape &shape, int grid, const NetDesc *d_descs,
+                  const int32_t *d_order, int n_nets, int32_t *d_counter, const int32_t *d_rules,
+                  int ns, int nr, uint32_t max_steps, int flags, hipStream_t s);
+int launch_jump_grid(const NetDesc *d_desc, int grid, hipStream_t s);
+int max_resident(const LaunchShape &shape, int ns, int nr, int *per_cu, int *n_cu);
+bool shape_supported(int wg);
+LaunchShape shape_for(int wg);
+
+enum { FLAG_JUMP = 1 };
+
+}  // namespace inet
+
+struct inet_net {
+  inet::CompiledRules rules;
+  int32_t n_nets = 0;
+  char *dev = nullptr;
+  size_t dev_bytes = 0;
+  // device pointers into dev
+  int32_t *d_rules = nullptr;
+  inet::NetDesc *d_descs = nullptr;
+  int32_t *d_order = nullptr;
+  int32_t *d_counter = nullptr;
+  int32_t *d_init_label = nullptr;
+  int32_t *d_init_port = nullptr;
+  int32_t *d_init_eq = nullptr;
+  std::vector<inet::NetDesc> descs;       // host copy of the descriptors
+  std::vector<int32_t> order;             // launch order
+  std::vector<int64_t> agent_off, eq_off;
+  std::vector<int32_t> n_names;
+  std::vector<std::vector<int32_t>> iface; // interface name ids per net
+  inet::NetState *d_states = nullptr;     // [n_nets], contiguous
+  unsigned long long *d_per_rule = nullptr; // [n_nets][nr], contiguous
+  std::vector<inet::NetState> states;     // from the last inet_results
+  bool results_valid = false;
+  inet_config cfg{0, 1, 0};
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool timed = false;
+  inet::NetState *h_states = nullptr;     // pinned staging
+};
+
+#endif

@@ -1,0 +1,213 @@
+"""GPU parity: the HIP evaluator (through the C ABI) against the CPU oracle,
+element by element on the canonical normal-form stream, the interaction
+count and the per-rule histogram (all integers: bit-exact)."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1404_0076_amd as P
+from paper_1404_0076_amd import nets
+
+from closed_forms import fib_count, mul_count, tree_count
+from gpu_util import assert_same, oracle_run
+
+pytestmark = pytest.mark.gpu
+R = nets.arith_rules()
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_examples.json")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu(rules, net, wg=0, **kw):
+    return P.reduce_net(rules, net, wg_size=wg, **kw)
+
+
+def test_paper_examples():
+    for case in json.load(open(GOLDEN))["cases"]:
+        say("paper example", case["net"])
+        rules = nets.add_rules()
+        net = nets.parse_net(nets.ARITH_SIG, case["net"])
+        res, nf, pr = gpu(rules, net)
+        assert res.status == P.OK
+        assert nf.tolist() == case["nf"]
+        assert res.interactions == case["interactions"]
+        assert_same((res, nf, pr), oracle_run(rules, net), case["net"])
+        if "rounds" in case:
+            assert res.steps == case["rounds"]
+
+
+SMALL = [
+    "<r | Add(Z, r) = S(Z)>", "<r | Add(S(Z), r) = Z>", "<r | Mul(Z, r) = Z>",
+    "<p, q | Dup(p, q) = Z>", "< | Era = Z>", "<r | Fib(r) = Z>", "<r | Fib2(r) = Z>",
+    "< | Era = S(Z)>", "<p, q | Dup(p, q) = S(Z)>", "<r | Fib(r) = S(Z)>",
+    "<r | Fib2(r) = S(Z)>", "<r | Mul(Z, r) = S(Z)>", "<r | S(r) = Z>", "<r | S(Z) = Add(Z, r)>",
+    "<r, y | Add(y, r) = S(S(Z))>", "<r | Add(b, r) = a, Mul(S(Z), a) = S(Z), Fib(b) = S(Z)>",
+]
+
+
+@pytest.mark.parametrize("text", SMALL)
+def test_small_nets(text):
+    say("small", text)
+    net = nets.parse_net(nets.ARITH_SIG, text)
+    assert_same(gpu(R, net), oracle_run(R, net), text)
+
+
+def test_chains():
+    sig = nets.Signature(names=["A", "B", "C"], arity=[1, 0, 0])
+    rules = nets.parse_rules(sig, ["A(r) = B -> r = C"])
+    for length in (1, 2, 5, 40):
+        links = ", ".join(f"x{i} = x{i+1}" for i in range(length - 1))
+        for end in ("B", "y"):
+            text = f"<r | A(r) = x0, {links + ', ' if links else ''}x{length - 1} = {end}>"
+            say("chain", length, end)
+            net = nets.parse_net(sig, text)
+            assert_same(gpu(rules, net), oracle_run(rules, net), text)
+
+
+def test_closed_loop():
+    sig = nets.Signature(names=["P", "Q"], arity=[1, 1])
+    rules = nets.parse_rules(sig, ["P(a) = Q(b) -> a = b"])
+    net = nets.parse_net(sig, "< | P(x) = Q(x)>")
+    res, nf, pr = gpu(rules, net)
+    assert res.status == P.OK and res.interactions == 1 and nf.tolist() == [0, 0]
+
+
+@pytest.mark.parametrize("a,b", [(0, 0), (1, 1), (3, 5), (17, 4), (40, 25), (120, 90)])
+def test_mul(a, b):
+    say("mul", a, b)
+    net = nets.mul_net(a, b)
+    g = gpu(R, net)
+    assert g[0].interactions == mul_count(a, b)
+    assert_same(g, oracle_run(R, net), f"mul {a} {b}")
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 5, 9, 14])
+def test_fib(n):
+    say("fib", n)
+    net = nets.fib_net(n)
+    g = gpu(R, net)
+    assert g[0].interactions == fib_count(n)
+    assert_same(g, oracle_run(R, net), f"fib {n}")
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_random_expressions(seed):
+    say("expr", seed)
+    net = nets.random_expr_net(seed, budget=12, max_num=5)
+    assert_same(gpu(R, net), oracle_run(R, net), f"expr {seed}")
+
+
+@pytest.mark.parametrize("wg", [64, 128, 256, 512, 1024])
+def test_launch_shapes_agree(wg):
+    # uniform confluence: the launch geometry changes the schedule only
+    for net in (nets.mul_net(30, 41), nets.fib_net(12), nets.config1_add_tree(3, 64, 30),
+                nets.random_expr_net(7, 14, 6)):
+        say("shape", wg, net.meta.get("family"))
+        assert_same(gpu(R, net, wg=wg), oracle_run(R, net), f"wg {wg}")
+
+
+def test_steps_equal_oracle_rounds():
+    # one GPU step reduces every active pair present after com has run to
+    # closure: exactly the oracle's maximal parallel rounds
+    for net in (nets.fib_net(10), nets.mul_net(12, 9), nets.config1_add_tree(1, 32, 20)):
+        res, _, _ = gpu(R, net)
+        ref = oracle.reduce(R, net, schedule="rounds")
+        say("rounds", res.steps, ref.rounds)
+        assert res.steps == ref.rounds
+
+
+def test_stuck_residuals():
+    for text in ("<r | S(r) = Z>", "<r, q | S(r) = Z, Add(q, y) = Fib(y)>"):
+        say("stuck", text)
+        net = nets.parse_net(nets.ARITH_SIG, text)
+        g = gpu(R, net)
+        assert g[0].status == P.STUCK
+        assert_same(g, oracle_run(R, net), text)
+
+
+def test_resume_after_step_limit():
+    net = nets.fib_net(11)
+    ref = oracle_run(R, net)
+    h = P.load(R, net, agent_cap=1 << 16, name_cap=1 << 18)
+    steps = 0
+    for i in range(10000):
+        res = h.reduce(max_steps=7)[0]
+        if res.status != P.ELIMIT:
+            break
+        assert res.steps == steps + 7
+        steps = res.steps
+    assert res.status == P.OK
+    assert_same((res, h.readback(0), h.per_rule(0)), ref, "resume")
+    h.free()
+
+
+def test_out_of_memory_reported():
+    net = nets.mul_net(30, 30)
+    h = P.load(R, net, agent_cap=net.n_agents + 8, name_cap=net.n_names + 8)
+    res = h.reduce()[0]
+    assert res.status == P.ENOMEM
+    h.free()
+
+
+def test_reset_repeats_exactly():
+    net = nets.random_expr_net(3, 12, 5)
+    ref = oracle_run(R, net)
+    h = P.load(R, net, agent_cap=1 << 16, name_cap=1 << 18)
+    for rep in range(3):
+        h.reset()
+        res = h.reduce()[0]
+        assert_same((res, h.readback(0), h.per_rule(0)), ref, f"rep {rep}")
+    h.free()
+
+
+def test_batch_matches_single_and_oracle():
+    batch = [nets.random_expr_net(s, 12, 5) for s in range(40)] + \
+            [nets.mul_net(a, b) for a, b in ((5, 7), (0, 3), (9, 0))] + \
+            [nets.fib_net(n) for n in (0, 3, 8, 11)] + \
+            [nets.config1_add_tree(s, 16, 12) for s in range(4)] + \
+            [nets.parse_net(nets.ARITH_SIG, "<r | S(r) = Z>")]
+    caps = [1 << 15] * len(batch)
+    for wg in (64, 256):
+        say("batch", len(batch), "wg", wg)
+        h = P.batch_load(R, batch, agent_caps=caps, name_caps=[1 << 17] * len(batch))
+        h.set_config(wg_size=wg)
+        rs = h.reduce()
+        for i, net in enumerate(batch):
+            assert_same((rs[i], h.readback(i), h.per_rule(i)), oracle_run(R, net), f"net {i}")
+        h.free()
+
+
+@pytest.mark.slow
+def test_config1_add_tree_full():
+    net = nets.config1_add_tree(0)
+    say("config1", net.n_agents)
+    g = gpu(R, net, agent_cap=1 << 20, name_cap=1 << 22)
+    assert g[0].interactions == tree_count(net.meta["values"])
+    assert_same(g, oracle_run(R, net), "config1")
+
+
+@pytest.mark.slow
+def test_config2_mul_full():
+    net = nets.config2_mul(0)
+    a, b = net.meta["a"], net.meta["b"]
+    say("config2", a, b)
+    g = gpu(R, net, agent_cap=a * b + 4 * (a + b) + 4096, name_cap=4 * a * b + 8 * (a + b) + 4096)
+    assert g[0].interactions == mul_count(a, b)
+    assert_same(g, oracle_run(R, net), "config2")
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("n", [20, 23])
+def test_config3_fib_full(n):
+    say("config3", n)
+    net = nets.fib_net(n)
+    g = gpu(R, net, agent_cap=4 * fib_count(n), name_cap=8 * fib_count(n))
+    assert g[0].interactions == fib_count(n)
+    assert_same(g, oracle_run(R, net), f"fib {n}")
