@@ -479,19 +479,20 @@ def poisson_arrivals(seed: int, rate: float, duration: float) -> np.ndarray:
 
 
 def random_expr_net(seed: int, budget: int = 12, max_num: int = 4,
-                    ops=("Add", "Mul", "Fib"), fib_budget: int = 2) -> Net:
+                    ops=("Add", "Mul", "Fib"), fib_budget: int = 2, op_depth: int = 2) -> Net:
     """A random arithmetic expression over the ARITH system as one net:
     e ::= S^k Z | Add(e, e) | Mul(e, e) | Fib(e).  Sub-results are connected
     through names, so the net has several initial equations.  The expression
     tree is returned in ``meta["expr"]`` as nested tuples
     ``("num", k) | ("add", e1, e2) | ("mul", e1, e2) | ("fib", e)`` where e1 is
-    the operand attached to the operator's principal port."""
+    the operand attached to the operator's principal port.  The top
+    ``op_depth`` levels are always operators."""
     rng = np.random.Generator(np.random.PCG64(seed))
     nb = NetBuilder(ARITH_SIG)
     root = nb.name()
 
-    def gen(res_name: int, budget: int):
-        if budget <= 0 or rng.random() < 0.3:
+    def gen(res_name: int, budget: int, depth: int = 0):
+        if budget <= 0 or (depth >= op_depth and rng.random() < 0.3):
             k = int(rng.integers(0, max_num + 1))
             nb.eq(res_name, nb.numeral(k))
             return ("num", k)
@@ -499,13 +500,13 @@ def random_expr_net(seed: int, budget: int = 12, max_num: int = 4,
         if op == "Fib":
             x = nb.name()
             nb.eq(nb.agent(FIB, res_name), x)
-            return ("fib", gen(x, min(budget - 1, fib_budget)))
+            return ("fib", gen(x, min(budget - 1, fib_budget), depth + 1))
         x = nb.name()
         y = nb.name()
         lab = ADD if op == "Add" else MUL
         nb.eq(nb.agent(lab, y, res_name), x)
-        e1 = gen(x, budget - 2)
-        e2 = gen(y, budget - 2)
+        e1 = gen(x, budget - 2, depth + 1)
+        e2 = gen(y, budget - 2, depth + 1)
         return (op.lower(), e1, e2)
 
     expr = gen(root, budget)

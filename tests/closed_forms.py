@@ -39,11 +39,10 @@ def fib_count(n: int) -> int:
     """T(0) = 1 (Fib><Z), T(1) = 2 (Fib><S, Fib2><Z); for n >= 2 Fib><S and
     Fib2><S (2), the Dup of S^(n-2) Z (n-1), then Fib(n-2) and Fib(n-1) and
     the Add consuming fib(n-2) (fib(n-2)+1)."""
-    if n == 0:
-        return 1
-    if n == 1:
-        return 2
-    return fib_count(n - 1) + fib_count(n - 2) + fib_value(n - 2) + n + 2
+    t = [1, 2]
+    for k in range(2, n + 1):
+        t.append(t[k - 1] + t[k - 2] + fib_value(k - 2) + k + 2)
+    return t[n]
 
 
 def tree_count(values) -> int:
@@ -69,6 +68,37 @@ def expr_value(e) -> int:
     if e[0] == "mul":
         return expr_value(e[1]) * expr_value(e[2])
     return fib_value(expr_value(e[1]))
+
+
+def small_exprs(count: int, budget: int, max_num: int, limit: int, min_count: int = 1,
+                **kw):
+    """The first ``count`` seeds whose expression needs between min_count and
+    limit interactions (values are checked first so huge ones are skipped
+    without building their counts)."""
+    from paper_1404_0076_amd import nets
+    out = []
+    seed = 0
+    while len(out) < count and seed < 100000:
+        net = nets.random_expr_net(seed, budget=budget, max_num=max_num, **kw)
+        e = net.meta["expr"]
+        if _bounded(e, limit):
+            c = expr_count(e)
+            if min_count <= c <= limit:
+                out.append((seed, net))
+        seed += 1
+    return out
+
+
+def _bounded(e, limit) -> bool:
+    """True when every intermediate value is small enough to count cheaply."""
+    if e[0] == "num":
+        return True
+    if not all(_bounded(s, limit) for s in e[1:]):
+        return False
+    v = expr_value(e)
+    if e[0] == "fib":
+        return expr_value(e[1]) <= 40
+    return v <= limit
 
 
 def expr_count(e) -> int:

@@ -7,7 +7,9 @@ import oracle
 from paper_1404_0076_amd import nets
 
 from closed_forms import (add_count, expr_count, expr_value, fib_count, fib_value, mul_count,
-                          mul_per_rule, rhs_agent_counts, tree_count)
+                          mul_per_rule, rhs_agent_counts, small_exprs, tree_count)
+
+EXPRS = small_exprs(40, 10, 4, 300_000)
 
 R = nets.arith_rules()
 RULE_NAMES = ["Add><S", "Add><Z", "Mul><S", "Mul><Z", "Dup><S", "Dup><Z", "Era><S",
@@ -74,9 +76,8 @@ def test_add_tree(seed, leaves, vmax):
     assert _nat(res) == sum(vals)
 
 
-@pytest.mark.parametrize("seed", range(40))
-def test_random_expressions(seed):
-    net = nets.random_expr_net(seed, budget=10, max_num=4)
+@pytest.mark.parametrize("seed,net", EXPRS, ids=[str(s) for s, _ in EXPRS])
+def test_random_expressions(seed, net):
     e = net.meta["expr"]
     res = oracle.reduce(R, net)
     assert res.status == oracle.OK
@@ -84,8 +85,9 @@ def test_random_expressions(seed):
     assert _nat(res) == expr_value(e)
 
 
-@pytest.mark.parametrize("net", [nets.fib_net(9), nets.mul_net(6, 7), nets.random_expr_net(5, 10)],
-                         ids=["fib9", "mul6x7", "expr5"])
+@pytest.mark.parametrize("net", [nets.fib_net(9), nets.mul_net(6, 7),
+                                 small_exprs(1, 10, 4, 5000, min_count=500)[0][1]],
+                         ids=["fib9", "mul6x7", "expr"])
 def test_live_agent_balance(net):
     # every int removes its two agents and adds the agents of its right-hand
     # side, so live agents = initial + sum_r count_r * (|RHS_r| - 2)

@@ -7,6 +7,8 @@ import pytest
 import oracle
 from paper_1404_0076_amd import nets
 
+from closed_forms import small_exprs
+
 R = nets.arith_rules()
 
 TINY = [
@@ -31,20 +33,20 @@ def test_every_schedule_same_outcome(text):
     assert res.nf.tolist() == ref.nf.tolist() and res.interactions == ref.interactions
 
 
-@pytest.mark.parametrize("seed", range(12))
-def test_random_expr_enumerated(seed):
-    net = nets.random_expr_net(seed, budget=4, max_num=2, fib_budget=0)
+TINY_EXPRS = small_exprs(12, 4, 2, 12, min_count=2, fib_budget=0)
+MID_EXPRS = small_exprs(10, 12, 5, 50_000, min_count=100)
+
+
+@pytest.mark.parametrize("seed,net", TINY_EXPRS, ids=[str(s) for s, _ in TINY_EXPRS])
+def test_random_expr_enumerated(seed, net):
     ref = oracle.reduce(R, net)
-    if ref.interactions > 14:
-        pytest.skip("too many interleavings to enumerate")
     res = oracle.reduce(R, net, schedule="enumerate", max_interactions=300000)
     assert res.status == oracle.OK and res.n_outcomes == 1
     assert res.nf.tolist() == ref.nf.tolist()
 
 
-@pytest.mark.parametrize("seed", range(10))
-def test_schedules_agree(seed):
-    net = nets.random_expr_net(seed, budget=12, max_num=5)
+@pytest.mark.parametrize("seed,net", MID_EXPRS, ids=[str(s) for s, _ in MID_EXPRS])
+def test_schedules_agree(seed, net):
     outs = []
     for sched, s in [("fifo", 0), ("lifo", 0), ("rounds", 0), ("random", 1), ("random", 99)]:
         for eager in (False, True):

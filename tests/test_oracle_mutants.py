@@ -2,13 +2,15 @@
 each be caught by the pins: a transposed operand, a lost orientation swap, a
 dropped right-hand-side equation, com counted as an interaction."""
 import os
+import subprocess
+import sys
 
 import pytest
 
 import oracle
 from paper_1404_0076_amd import nets
 
-from closed_forms import expr_count, expr_value, fib_count, mul_count
+from closed_forms import expr_count, expr_value, fib_count, mul_count, small_exprs
 
 R = nets.arith_rules()
 
@@ -21,8 +23,7 @@ def _pins_hold(lib):
                       and oracle.decode_nat(r.nf, 0, 1) == a * b)
     r = oracle.reduce(R, nets.fib_net(6), lib=lib)
     checks.append(r.status == 0 and r.interactions == fib_count(6))
-    for seed in range(4):
-        net = nets.random_expr_net(seed, budget=8, max_num=3)
+    for seed, net in small_exprs(4, 8, 3, 20_000, min_count=20):
         r = oracle.reduce(R, net, lib=lib)
         e = net.meta["expr"]
         checks.append(r.status == 0 and r.interactions == expr_count(e)
@@ -43,7 +44,13 @@ def test_correct_oracle_passes_pins():
 
 @pytest.mark.parametrize("mutant", [1, 2, 3, 4])
 def test_mutant_caught(mutant, tmp_path):
+    # a planted mistake may also corrupt the oracle's state and crash it: the
+    # pins run in a child process, and a crash counts as caught
     path = oracle.build(out=str(tmp_path / f"liboracle_m{mutant}.so"),
                         defines=[f"ORC_MUTANT={mutant}"])
-    lib = oracle.load_library(path)
-    assert not _pins_hold(lib)
+    here = os.path.dirname(os.path.abspath(__file__))
+    code = ("import sys; sys.path[:0] = [%r, %r]; import oracle, test_oracle_mutants as t; "
+            "sys.exit(0 if t._pins_hold(oracle.load_library(%r)) else 3)"
+            % (here, os.path.dirname(here), path))
+    rc = subprocess.run([sys.executable, "-c", code], capture_output=True, timeout=300).returncode
+    assert rc != 0

@@ -12,7 +12,7 @@ import oracle
 import paper_1404_0076_amd as P
 from paper_1404_0076_amd import nets
 
-from closed_forms import fib_count, mul_count, tree_count
+from closed_forms import expr_count, fib_count, mul_count, small_exprs, tree_count
 from gpu_util import assert_same, oracle_run
 
 pytestmark = pytest.mark.gpu
@@ -97,10 +97,13 @@ def test_fib(n):
     assert_same(g, oracle_run(R, net), f"fib {n}")
 
 
-@pytest.mark.parametrize("seed", range(30))
-def test_random_expressions(seed):
-    say("expr", seed)
-    net = nets.random_expr_net(seed, budget=12, max_num=5)
+EXPRS = small_exprs(30, 12, 5, 3_000_000)
+MID = small_exprs(1, 12, 6, 20_000, min_count=5_000)[0][1]
+
+
+@pytest.mark.parametrize("seed,net", EXPRS, ids=[str(s) for s, _ in EXPRS])
+def test_random_expressions(seed, net):
+    say("expr", seed, expr_count(net.meta["expr"]))
     assert_same(gpu(R, net), oracle_run(R, net), f"expr {seed}")
 
 
@@ -108,7 +111,7 @@ def test_random_expressions(seed):
 def test_launch_shapes_agree(wg):
     # uniform confluence: the launch geometry changes the schedule only
     for net in (nets.mul_net(30, 41), nets.fib_net(12), nets.config1_add_tree(3, 64, 30),
-                nets.random_expr_net(7, 14, 6)):
+                MID):
         say("shape", wg, net.meta.get("family"))
         assert_same(gpu(R, net, wg=wg), oracle_run(R, net), f"wg {wg}")
 
@@ -157,7 +160,7 @@ def test_out_of_memory_reported():
 
 
 def test_reset_repeats_exactly():
-    net = nets.random_expr_net(3, 12, 5)
+    net = MID
     ref = oracle_run(R, net)
     h = P.load(R, net, agent_cap=1 << 16, name_cap=1 << 18)
     for rep in range(3):
@@ -168,7 +171,7 @@ def test_reset_repeats_exactly():
 
 
 def test_batch_matches_single_and_oracle():
-    batch = [nets.random_expr_net(s, 12, 5) for s in range(40)] + \
+    batch = [n for _, n in small_exprs(40, 12, 5, 200_000)] + \
             [nets.mul_net(a, b) for a, b in ((5, 7), (0, 3), (9, 0))] + \
             [nets.fib_net(n) for n in (0, 3, 8, 11)] + \
             [nets.config1_add_tree(s, 16, 12) for s in range(4)] + \
