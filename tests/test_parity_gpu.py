@@ -176,14 +176,15 @@ def test_batch_matches_single_and_oracle():
             [nets.fib_net(n) for n in (0, 3, 8, 11)] + \
             [nets.config1_add_tree(s, 16, 12) for s in range(4)] + \
             [nets.parse_net(nets.ARITH_SIG, "<r | S(r) = Z>")]
-    caps = [1 << 15] * len(batch)
+    refs = [oracle_run(R, net) for net in batch]
+    caps = [net.n_agents + 4 * r.interactions + 1024 for net, r in zip(batch, refs)]
     for wg in (64, 256):
         say("batch", len(batch), "wg", wg)
-        h = P.batch_load(R, batch, agent_caps=caps, name_caps=[1 << 17] * len(batch))
+        h = P.batch_load(R, batch, agent_caps=caps, name_caps=[4 * c for c in caps])
         h.set_config(wg_size=wg)
         rs = h.reduce()
         for i, net in enumerate(batch):
-            assert_same((rs[i], h.readback(i), h.per_rule(i)), oracle_run(R, net), f"net {i}")
+            assert_same((rs[i], h.readback(i), h.per_rule(i)), refs[i], f"net {i}")
         h.free()
 
 
