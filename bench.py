@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true", help="skip the single-net side measurement")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (to scale HBM counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -108,6 +110,15 @@ def main():
     from paper_1404_0076_amd import nets
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        x = torch.ones(args.copy_calibration, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_calibration, "reps": 3}), flush=True)
+        return
     R = nets.arith_rules()
     if args.workload == "batch":
         net_list = nets.config4_batch(seed=args.seed, n_nets=args.n_nets)

@@ -276,16 +276,39 @@ __global__ __launch_bounds__(WG) void k_reduce(const NetDesc *__restrict__ descs
           for (int f = 0; f < nfresh; f++) D.bind[my_n + f] = EMPTY;
           atomicAdd(&s_rc[rid], 1ull);
         }
+        // com: the first exchange of every link equation is issued before
+        // any result is awaited (independent cells), then chains continue
         int loops = 0;
+        int eu[MAXEQ], ev[MAXEQ], eo[MAXEQ];
+#pragma unroll
+        for (int j = 0; j < MAXEQ; j++) {
+          eo[j] = EMPTY;
+          eu[j] = 0;
+          ev[j] = 0;
+          if (j < neq) {
+            int u = resolve(T[RT_EQ + 2 * j], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
+            int v = resolve(T[RT_EQ + 2 * j + 1], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
+            if (u >= 0) { const int t = u; u = v; v = t; }
+            eu[j] = u;
+            ev[j] = v;
+            if (u < 0 && u != v) eo[j] = xchg(&D.bind[~u], v);
+          }
+        }
+#pragma unroll
         for (int j = 0; j < MAXEQ; j++) {
           const bool has = j < neq;
           if (ballot(has) == 0ull) break;
           bool prod = false;
           int ou = 0, ov = 0;
           if (has) {
-            const int u = resolve(T[RT_EQ + 2 * j], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
-            const int v = resolve(T[RT_EQ + 2 * j + 1], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
-            prod = link(u, v, D.bind, ou, ov, loops, &s_status);
+            const int u = eu[j], v = ev[j];
+            if (u >= 0) {                       // both sides agents
+              prod = true; ou = u; ov = v;
+            } else if (u == v) {
+              loops++;                          // x = x: closed loop
+            } else if (eo[j] != EMPTY) {        // second occurrence: old = v
+              prod = link(eo[j], v, D.bind, ou, ov, loops, &s_status);
+            }
           }
           wave_push(prod, ou, ov, nq_l, QCAP, nq_g, D.qcap, &s_cnt[cn], &s_status);
         }
