@@ -31,7 +31,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def size_batch(P, R, net_list, wg):
+def size_batch(P, R, net_list, wg, engine=0):
     """Find exact heap needs (agents and name cells are deterministic: they
     depend only on the per-rule counts) by reducing once with growing caps."""
     n = len(net_list)
@@ -47,7 +47,7 @@ def size_batch(P, R, net_list, wg):
             break
         h = P.batch_load(R, [net_list[i] for i in pending], agent_caps=acap[pending],
                          name_caps=ncap[pending])
-        h.set_config(wg_size=wg)
+        h.set_config(wg_size=wg, engine=engine)
         rs = h.reduce()
         h.free()
         again = []
@@ -83,16 +83,53 @@ def cpu_baseline(R, net_list, seconds):
                       f"{dt:.1f} s, single thread"}
 
 
+def bench_serve(args, P, R, nets, torch):
+    """Served workload: Poisson arrivals of nets drawn from the batch mix."""
+    from paper_1404_0076_amd.serve import serve
+    pool = nets.config5_pool(seed=2, n_nets=args.pool)
+    log(f"sizing pool of {len(pool)}")
+    used_a, used_n, steps, inter = size_batch(P, R, pool, args.wg or 256)
+    caps = list(zip(used_a + 64, used_n + 64))
+    arrivals = nets.poisson_arrivals(3, args.rate, args.duration)
+    rng = np.random.Generator(np.random.PCG64(4))
+    pick = rng.integers(0, len(pool), len(arrivals))
+    log(f"serving {len(arrivals)} requests at {args.rate}/s")
+    rep = serve(R, pool, arrivals, pick, caps=caps, max_slots=8192, workspace_bytes=48 << 30,
+                round_steps=args.round_steps, wg_size=args.wg)
+    bad = [s for s in rep.served if s.status not in (P.OK, P.STUCK)]
+    if bad:
+        raise RuntimeError(f"{len(bad)} requests failed")
+    exp = int(sum(inter[j] for j in pick))
+    assert rep.interactions == exp, "served interaction count differs from the sizing pass"
+    out = {
+        "metric": METRIC, "value": rep.interactions / rep.wall, "unit": "interactions/s",
+        "n_gpus": 1, "steps": rep.rounds, "warmup": 0, "ms_per_step": rep.wall * 1e3 / max(1, rep.rounds),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"served: Poisson arrivals at {args.rate:g} nets/s for {args.duration:g} s "
+                               f"from a pool of {len(pool)} nets (batch mix, seed 2)",
+                   "round_steps": args.round_steps, "requests": len(arrivals)},
+        "latency_ms": {"p50": rep.latency_ms(50), "p99": rep.latency_ms(99), "max": rep.latency_ms(100)},
+        "rounds": rep.rounds, "max_resident": rep.max_resident, "wall_s": rep.wall,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="batch", choices=["batch", "mul", "fib", "addtree"])
+    ap.add_argument("--workload", default="batch", choices=["batch", "mul", "fib", "addtree", "serve"])
+    ap.add_argument("--rate", type=float, default=1.0e4, help="serve: Poisson arrival rate (nets/s)")
+    ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals")
+    ap.add_argument("--pool", type=int, default=8192, help="serve: request pool size")
+    ap.add_argument("--round-steps", type=int, default=256, help="serve: step budget per round")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--n-nets", type=int, default=4096)
     ap.add_argument("--fib-n", type=int, default=27)
     ap.add_argument("--wg", type=int, default=0)
+    ap.add_argument("--engine", type=int, default=0, help="0 default, 1 interpreter, 2 rule-uniform")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true", help="skip the single-net side measurement")
@@ -120,6 +157,8 @@ def main():
         print(json.dumps({"copy_bytes": args.copy_calibration, "reps": 3}), flush=True)
         return
     R = nets.arith_rules()
+    if args.workload == "serve":
+        return bench_serve(args, P, R, nets, torch)
     if args.workload == "batch":
         net_list = nets.config4_batch(seed=args.seed, n_nets=args.n_nets)
         workload = {"workload": f"batch of {args.n_nets} nets (Add tree / Mul / Fib mix, "
@@ -138,10 +177,10 @@ def main():
                                 f"seed {args.seed}"}
     wg = args.wg or (256 if len(net_list) > 1 else 1024)
     log(f"sizing {len(net_list)} nets (wg {wg})")
-    used_a, used_n, steps, inter = size_batch(P, R, net_list, wg)
+    used_a, used_n, steps, inter = size_batch(P, R, net_list, wg, args.engine)
     order = np.argsort(-steps, kind="stable").astype(np.int32)  # longest critical path first
     h = P.batch_load(R, net_list, agent_caps=used_a + 64, name_caps=used_n + 64)
-    h.set_config(wg_size=wg)
+    h.set_config(wg_size=wg, engine=args.engine)
     h.set_order(order)
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
@@ -181,7 +220,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "interactions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
-        "data": "synthetic", "config": dict(workload, wg_size=wg,
+        "data": "synthetic", "config": dict(workload, wg_size=wg, engine=h.get_config()["engine"],
                                             interactions_per_step=total),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,

@@ -121,6 +121,8 @@ typedef struct {
   int32_t wg_size;          /* lanes per net engine: 64,128,256,512,1024   */
   int32_t jump;             /* 1: compress name chains after the loop      */
   int32_t max_resident;     /* cap on simultaneously resident net engines  */
+  int32_t engine;           /* 0 default; 1 per-lane rule interpreter;
+                               2 rule-uniform execution (default)          */
 } inet_config;
 
 typedef struct inet_net inet_net;
@@ -175,6 +177,14 @@ int inet_reduce(inet_net *h, hipStream_t stream, uint64_t max_steps, inet_result
 /* Restore every net to its loaded state (device to device, on stream). */
 int inet_reset(inet_net *h, hipStream_t stream);
 
+/* One batched step captured as a HIP graph held by the handle: restore every
+ * net (device to device), clear the net counter, the persistent reduction and
+ * the pointer-jumping pass.  Capture runs on a private stream; the graph can
+ * then be replayed on any stream with inet_graph_launch (results as after
+ * inet_reduce_async).  Recapture after inet_set_config / inet_set_order. */
+int inet_graph_capture(inet_net *h, uint64_t max_steps);
+int inet_graph_launch(inet_net *h, hipStream_t stream);
+
 /* Canonical normal-form stream of net i (the sub* col* read-back of Theorem
  * 1, Section 2.2).  Needs inet_results first.  cap too small: INET_ERANGE
  * with *len set to the required words. */
@@ -204,6 +214,40 @@ const char *inet_strerror(int status);
 /* Kernel time of the last reduction launch on this handle, measured with HIP
  * events on the launch stream (ms); -1 if not available yet. */
 float inet_last_kernel_ms(inet_net *h);
+
+/* ------------------------------------------------------------------------
+ * Continuous batching (serving).  A server owns one caller-provided device
+ * buffer and up to max_slots resident nets.  inet_server_submit admits a net
+ * when a slot and a free byte range of its workspace are available (else
+ * INET_EAGAIN: admission is by free device bytes), uploads it on `stream`
+ * and makes it part of the next round.  inet_server_step launches one round:
+ * every running net advances by at most max_steps parallel steps, keeping its
+ * heap and frontier resident between rounds.  inet_server_poll waits for the
+ * round on `stream` and reports the tickets of nets that finished (normal
+ * form, or an error such as INET_ENOMEM); their results stay readable until
+ * inet_server_release returns the slot and memory.  Calls on one server must
+ * not overlap. */
+typedef struct inet_server inet_server;
+int inet_server_create(const inet_rules *rules, int32_t max_slots, void *dev, size_t dev_bytes,
+                       inet_server **out);
+int inet_server_set_config(inet_server *s, const inet_config *cfg);
+/* device bytes one admitted net occupies (caps as for inet_workspace_bytes) */
+int inet_server_net_bytes(const inet_server *s, int32_t n_agents, int32_t n_eqs, int32_t n_names,
+                          int64_t agent_cap, int64_t name_cap, int64_t *bytes);
+int inet_server_submit(inet_server *s, const int32_t *label, const int32_t *port, int32_t n_agents,
+                       const int32_t *eq_lhs, const int32_t *eq_rhs, int32_t n_eqs, int32_t n_names,
+                       int64_t agent_cap, int64_t name_cap, hipStream_t stream, int64_t *ticket);
+int inet_server_step(inet_server *s, hipStream_t stream, uint32_t max_steps);
+int inet_server_poll(inet_server *s, hipStream_t stream, int64_t *done, int32_t cap,
+                     int32_t *n_done);
+/* result of a finished net; buf/len as for inet_readback (len NULL: counters only) */
+int inet_server_result(inet_server *s, int64_t ticket, inet_result *res, int32_t *buf, int64_t cap,
+                       int64_t *len);
+int inet_server_per_rule(inet_server *s, int64_t ticket, uint64_t *counts, int32_t cap);
+int inet_server_release(inet_server *s, int64_t ticket);
+int inet_server_stats(const inet_server *s, int64_t *free_bytes, int32_t *free_slots,
+                      int32_t *running);
+void inet_server_free(inet_server *s);
 
 #ifdef __cplusplus
 }

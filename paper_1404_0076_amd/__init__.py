@@ -25,7 +25,10 @@ EXPORTS = [
     "inet_workspace_bytes", "inet_load", "inet_batch_load", "inet_set_config", "inet_get_config",
     "inet_set_order", "inet_reduce_async", "inet_results", "inet_reduce", "inet_reset",
     "inet_readback", "inet_per_rule", "inet_rule_bytes", "inet_num_nets", "inet_free",
-    "inet_strerror", "inet_last_kernel_ms", "inet_rules_check",
+    "inet_strerror", "inet_last_kernel_ms", "inet_rules_check", "inet_graph_capture",
+    "inet_graph_launch", "inet_server_create", "inet_server_set_config", "inet_server_net_bytes",
+    "inet_server_submit", "inet_server_step", "inet_server_poll", "inet_server_result",
+    "inet_server_per_rule", "inet_server_release", "inet_server_stats", "inet_server_free",
 ]
 
 
@@ -50,7 +53,7 @@ class _Result(ctypes.Structure):
 
 class _Config(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("jump", ctypes.c_int32),
-                ("max_resident", ctypes.c_int32)]
+                ("max_resident", ctypes.c_int32), ("engine", ctypes.c_int32)]
 
 
 _lib = None
@@ -76,6 +79,16 @@ def library():
             "inet_readback": [_P, _I32, _P, _I64, _P], "inet_per_rule": [_P, _I32, _P, _I32],
             "inet_rule_bytes": [_P, _P, _I32], "inet_num_nets": [_P],
             "inet_rules_check": [_P, _P, _P, _P, _P, _I32],
+            "inet_graph_capture": [_P, _U64], "inet_graph_launch": [_P, _P],
+            "inet_server_create": [_P, _I32, _P, ctypes.c_size_t, _P],
+            "inet_server_set_config": [_P, _P],
+            "inet_server_net_bytes": [_P, _I32, _I32, _I32, _I64, _I64, _P],
+            "inet_server_submit": [_P, _P, _P, _I32, _P, _P, _I32, _I32, _I64, _I64, _P, _P],
+            "inet_server_step": [_P, _P, ctypes.c_uint32],
+            "inet_server_poll": [_P, _P, _P, _I32, _P],
+            "inet_server_result": [_P, _I64, _P, _P, _I64, _P],
+            "inet_server_per_rule": [_P, _I64, _P, _I32],
+            "inet_server_release": [_P, _I64], "inet_server_stats": [_P, _P, _P, _P],
         }
         for name, args in sig.items():
             f = getattr(lib, name)
@@ -83,6 +96,8 @@ def library():
             f.restype = ctypes.c_int
         lib.inet_free.argtypes = [_P]
         lib.inet_free.restype = None
+        lib.inet_server_free.argtypes = [_P]
+        lib.inet_server_free.restype = None
         lib.inet_strerror.argtypes = [ctypes.c_int]
         lib.inet_strerror.restype = ctypes.c_char_p
         lib.inet_last_kernel_ms.argtypes = [_P]
@@ -180,14 +195,16 @@ class Handle:
             raise InetError(rc, what)
         return rc
 
-    def set_config(self, wg_size: int = 0, jump: bool = True, max_resident: int = 0):
-        cfg = _Config(wg_size, 1 if jump else 0, max_resident)
+    def set_config(self, wg_size: int = 0, jump: bool = True, max_resident: int = 0,
+                   engine: int = 0):
+        cfg = _Config(wg_size, 1 if jump else 0, max_resident, engine)
         self._check(library().inet_set_config(self._h, ctypes.byref(cfg)), "inet_set_config")
 
     def get_config(self) -> dict:
         cfg = _Config()
         self._check(library().inet_get_config(self._h, ctypes.byref(cfg)), "inet_get_config")
-        return {"wg_size": cfg.wg_size, "jump": bool(cfg.jump), "max_resident": cfg.max_resident}
+        return {"wg_size": cfg.wg_size, "jump": bool(cfg.jump), "max_resident": cfg.max_resident,
+                "engine": cfg.engine}
 
     def set_order(self, order: Sequence[int]):
         o = _arr(order, np.int32)
@@ -236,6 +253,14 @@ class Handle:
         out = np.zeros(max(1, self.rules.n_rules), dtype=np.int32)
         self._check(library().inet_rule_bytes(self._h, out.ctypes.data, out.size), "inet_rule_bytes")
         return out[: self.rules.n_rules]
+
+    def graph_capture(self, max_steps: int = 0):
+        """Capture restore + reduce as a HIP graph (inet_graph_capture)."""
+        self._check(library().inet_graph_capture(self._h, max_steps), "inet_graph_capture")
+
+    def graph_launch(self, stream=None):
+        s, _ = _stream_handle(stream)
+        self._check(library().inet_graph_launch(self._h, s), "inet_graph_launch")
 
     def last_kernel_ms(self) -> float:
         return float(library().inet_last_kernel_ms(self._h))
@@ -298,14 +323,14 @@ def load(rules, net: "nets.Net", agent_cap: int = 0, name_cap: int = 0, stream=N
 
 
 def reduce_net(rules, net, agent_cap: int = 0, name_cap: int = 0, wg_size: int = 0,
-               max_retries: int = 6, jump: bool = True):
+               max_retries: int = 6, jump: bool = True, engine: int = 0):
     """Load, reduce and read back one net; on ENOMEM reload with 4x capacity.
     Returns (Result, normal-form stream, per-rule counts)."""
     agent_cap = agent_cap or max(4 * net.n_agents + 4096, 1 << 16)
     name_cap = name_cap or 4 * agent_cap
     for _ in range(max_retries):
         h = load(rules, net, agent_cap=agent_cap, name_cap=name_cap)
-        h.set_config(wg_size=wg_size, jump=jump)
+        h.set_config(wg_size=wg_size, jump=jump, engine=engine)
         res = h.reduce()[0]
         if res.status == ENOMEM:
             h.free()
@@ -317,6 +342,123 @@ def reduce_net(rules, net, agent_cap: int = 0, name_cap: int = 0, wg_size: int =
         h.free()
         return res, nf, pr
     raise InetError(ENOMEM, "reduce_net")
+
+
+def _result(r) -> Result:
+    return Result(r.status, r.n_stuck, r.interactions, r.steps, r.agents_used, r.names_used,
+                  r.max_frontier, r.loops)
+
+
+class Server:
+    """Continuous batching (inet_server_*): admit nets while others run."""
+
+    def __init__(self, rules, max_slots: int, workspace_bytes: int, device="cuda"):
+        import torch
+        self.rules = rules
+        self.R = RulesArg(rules)
+        self.workspace = torch.empty(workspace_bytes, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        rc = library().inet_server_create(self.R.ptr, max_slots, ctypes.c_void_p(self.workspace.data_ptr()),
+                                          workspace_bytes, ctypes.byref(h))
+        if rc:
+            raise InetError(rc, "inet_server_create")
+        self._h = h
+        self.max_slots = max_slots
+
+    def set_config(self, wg_size: int = 0, jump: bool = True, max_resident: int = 0,
+                   engine: int = 0):
+        cfg = _Config(wg_size, 1 if jump else 0, max_resident, engine)
+        rc = library().inet_server_set_config(self._h, ctypes.byref(cfg))
+        if rc:
+            raise InetError(rc, "inet_server_set_config")
+
+    def net_bytes(self, net, agent_cap=0, name_cap=0) -> int:
+        out = ctypes.c_int64(0)
+        rc = library().inet_server_net_bytes(self._h, net.n_agents, net.n_eqs, net.n_names, agent_cap,
+                                             name_cap, ctypes.byref(out))
+        if rc:
+            raise InetError(rc, "inet_server_net_bytes")
+        return int(out.value)
+
+    def submit(self, net, agent_cap: int = 0, name_cap: int = 0, stream=None) -> Optional[int]:
+        """Ticket, or None when there is no room (INET_EAGAIN)."""
+        s, _ = _stream_handle(stream)
+        la, po = _arr(net.label, np.int32), _arr(net.port, np.int32)
+        el, er = _arr(net.eq_lhs, np.int32), _arr(net.eq_rhs, np.int32)
+        t = ctypes.c_int64(0)
+        rc = library().inet_server_submit(self._h, la.ctypes.data, po.ctypes.data, net.n_agents,
+                                          el.ctypes.data, er.ctypes.data, net.n_eqs, net.n_names,
+                                          agent_cap, name_cap, s, ctypes.byref(t))
+        if rc == EAGAIN:
+            return None
+        if rc:
+            raise InetError(rc, "inet_server_submit")
+        return int(t.value)
+
+    def step(self, max_steps: int, stream=None):
+        s, _ = _stream_handle(stream)
+        rc = library().inet_server_step(self._h, s, max_steps)
+        if rc:
+            raise InetError(rc, "inet_server_step")
+
+    def poll(self, stream=None) -> List[int]:
+        s, _ = _stream_handle(stream)
+        out = []
+        buf = np.zeros(1024, np.int64)
+        while True:
+            n = ctypes.c_int32(0)
+            rc = library().inet_server_poll(self._h, s, buf.ctypes.data, buf.size, ctypes.byref(n))
+            if rc:
+                raise InetError(rc, "inet_server_poll")
+            out.extend(int(x) for x in buf[: n.value])
+            if n.value < buf.size:
+                return out
+
+    def result(self, ticket: int, stream_out: bool = True):
+        r = _Result()
+        if not stream_out:
+            rc = library().inet_server_result(self._h, ticket, ctypes.byref(r), None, 0, None)
+            return _result(r), None
+        n = ctypes.c_int64(0)
+        rc = library().inet_server_result(self._h, ticket, ctypes.byref(r), None, 0, ctypes.byref(n))
+        res = _result(r)
+        if rc != ERANGE:
+            return res, None
+        buf = np.zeros(max(1, n.value), np.int32)
+        rc = library().inet_server_result(self._h, ticket, ctypes.byref(r), buf.ctypes.data, buf.size,
+                                          ctypes.byref(n))
+        if rc not in (OK, STUCK):
+            raise InetError(rc, "inet_server_result")
+        return res, buf[: n.value].copy()
+
+    def per_rule(self, ticket: int) -> np.ndarray:
+        out = np.zeros(max(1, self.rules.n_rules), np.uint64)
+        rc = library().inet_server_per_rule(self._h, ticket, out.ctypes.data, out.size)
+        if rc:
+            raise InetError(rc, "inet_server_per_rule")
+        return out[: self.rules.n_rules]
+
+    def release(self, ticket: int):
+        rc = library().inet_server_release(self._h, ticket)
+        if rc:
+            raise InetError(rc, "inet_server_release")
+
+    def stats(self) -> dict:
+        fb, fs, rn = ctypes.c_int64(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        library().inet_server_stats(self._h, ctypes.byref(fb), ctypes.byref(fs), ctypes.byref(rn))
+        return {"free_bytes": int(fb.value), "free_slots": int(fs.value), "running": int(rn.value)}
+
+    def free(self):
+        if getattr(self, "_h", None):
+            library().inet_server_free(self._h)
+            self._h = None
+            self.workspace = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def check_exports() -> List[str]:

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libinet.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["kernels.hip", "runtime.cpp", "rules.cpp", "readback.cpp"]
+SOURCES = ["kernels.hip", "runtime.cpp", "rules.cpp", "readback.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("INET_ARCH", "gfx950")
 

@@ -70,13 +70,14 @@ struct NetDesc {
   int2 *stuck;
   unsigned long long *per_rule;
   NetState *st;
+  // initial image (for reset): label[n], port[n][2], equations[n_eqs][2]
+  const int32_t *init_label;
+  const int32_t *init_port;
+  const int32_t *init_eq;
   int32_t agent_cap;
   int32_t name_cap;
   int32_t qcap;
   int32_t scap;
-  // initial image (for reset): offsets into the packed input copies
-  int64_t init_agent_off;
-  int64_t init_eq_off;
   int32_t n_agents0;
   int32_t n_eqs0;
   int32_t n_names0;

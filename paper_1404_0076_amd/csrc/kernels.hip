@@ -29,6 +29,30 @@
 
 namespace inet {
 
+// heap pointers as global-address-space pointers: loads, stores and atomics
+// then compile to global_* instructions (a flat access would also hold back
+// every wait on LDS results)
+typedef __attribute__((address_space(1))) int gint;
+struct Pair {  // an equation or an active pair (POD, usable in any address space)
+  int x, y;
+};
+__device__ __forceinline__ Pair mkpair(int x, int y) {
+  Pair p;
+  p.x = x;
+  p.y = y;
+  return p;
+}
+// in global memory a pair is one 64-bit word, x in the low half (the same
+// bytes as an int2 {x, y})
+typedef __attribute__((address_space(1))) unsigned long long gint2;
+__device__ __forceinline__ unsigned long long pk(int x, int y) {
+  return (unsigned long long)(unsigned)x | ((unsigned long long)(unsigned)y << 32);
+}
+__device__ __forceinline__ Pair unpk(unsigned long long w) {
+  return mkpair((int)(unsigned)w, (int)(unsigned)(w >> 32));
+}
+typedef __attribute__((address_space(1))) unsigned long long gu64;
+
 __device__ __forceinline__ int count_below(unsigned long long m) {
   return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
                                         __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
@@ -54,8 +78,8 @@ __device__ __forceinline__ int wave_scan16(int v, int *total) {
 }
 
 // append (u, v) for every lane with prod set; one LDS atomic per wave
-__device__ __forceinline__ void wave_push(bool prod, int u, int v, int2 *lds_q, int lds_cap,
-                                          int2 *g_q, int qcap, int *cnt, int *status) {
+__device__ __forceinline__ void wave_push(bool prod, int u, int v, Pair *lds_q, int lds_cap,
+                                          gint2 *g_q, int qcap, int *cnt, int *status) {
   const unsigned long long m = ballot(prod);
   if (m == 0ull) return;
   int base = 0;
@@ -63,13 +87,13 @@ __device__ __forceinline__ void wave_push(bool prod, int u, int v, int2 *lds_q, 
   base = first_lane_value(base);
   if (prod) {
     const int i = base + count_below(m);
-    if (i < lds_cap) lds_q[i] = make_int2(u, v);
-    else if (i < qcap) g_q[i] = make_int2(u, v);
+    if (i < lds_cap) lds_q[i] = mkpair(u, v);
+    else if (i < qcap) g_q[i] = pk(u, v);
     else *status = ST_ENOMEM;
   }
 }
 
-__device__ __forceinline__ int xchg(int *p, int v) {
+__device__ __forceinline__ int xchg(gint *p, int v) {
   return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
@@ -78,7 +102,7 @@ __device__ __forceinline__ int xchg(int *p, int v) {
 // finds a filled cell consumes both occurrences of that name, so a chain is
 // at most as long as the number of names; the guard only turns a broken
 // invariant into an error instead of a spin.
-__device__ __forceinline__ bool link(int u, int v, int *__restrict__ bind, int &ou, int &ov,
+__device__ __forceinline__ bool link(int u, int v, gint *__restrict__ bind, int &ou, int &ov,
                                      int &loops, int *status) {
   for (int guard = 0;; guard++) {
     if (u >= 0) {
@@ -101,9 +125,28 @@ __device__ __forceinline__ int resolve(int op, int a, int b, int pa0, int pa1, i
   return -1 - (my_n + idx);
 }
 
+// operand of a rule template whose code is uniform across the wave: the
+// kind/index tests become scalar branches and one move is left per lane
+__device__ __forceinline__ int resolve_u(int op, int a, int b, int pa0, int pa1, int pb0, int pb1,
+                                         int my_a, int my_n) {
+  const int kind = op >> 4, idx = op & 15;
+  if (kind == OP_AUX) {
+    if (idx == 0) return pa0;
+    if (idx == 1) return pa1;
+    if (idx == 2) return pb0;
+    return pb1;
+  }
+  if (kind == OP_NEW) {
+    if (idx == 0) return a;
+    if (idx == 1) return b;
+    return my_a + (idx - 2);
+  }
+  return -1 - (my_n + idx);
+}
+
 // pointer jumping over the cells [lo, hi) with stride: a cell whose value is
 // a name whose own cell is filled takes that cell's value (a com step)
-__device__ __forceinline__ void jump_cells(int *__restrict__ bind, int lo, int hi, int stride) {
+__device__ __forceinline__ void jump_cells(gint *__restrict__ bind, int lo, int hi, int stride) {
   for (int x = lo; x < hi; x += stride) {
     int v = bind[x];
     int hops = 0;
@@ -119,13 +162,202 @@ __device__ __forceinline__ void jump_cells(int *__restrict__ bind, int lo, int h
   }
 }
 
-template <int WG, int QCAP>
+// one pass of the interaction phase with the rule template interpreted per
+// lane (ENGINE 1)
+#define INET_PASS_ARGS                                                                    \
+  bool valid, int a, int b, int la, int lb, int pa0, int pa1, int pb0, int pb1, const NetDesc &D, \
+      gint *label, gint *port0, gint *port1, gint *bind, gint2 *stuck, const int *rule_of,        \
+      const int *templ, const int *arity, const int *__restrict__ g_templ,                          \
+      const int *__restrict__ g_arity, int ns, Pair *nq_l, gint2 *nq_g, int *ncnt, int *s_status,  \
+      int *s_agent_top, int *s_name_top, int *s_nstuck, int *s_loops, unsigned long long *s_rc
+
+template <int QCAP>
+__device__ __forceinline__ void stuck_push(bool stk, int a, int b, const NetDesc &D, gint2 *stuck,
+                                           int *s_nstuck, int *s_status) {
+  const unsigned long long m = ballot(stk);
+  if (m) {
+    int sb = 0;
+    if (__lane_id() == 0) sb = atomicAdd(s_nstuck, __popcll(m));
+    sb = first_lane_value(sb);
+    if (stk) {
+      const int si = sb + count_below(m);
+      if (si < D.scap) stuck[si] = pk(a, b);
+      else *s_status = ST_ENOMEM;
+    }
+  }
+}
+
+template <int QCAP>
+__device__ __forceinline__ void pass_interp(INET_PASS_ARGS) {
+  const int code = valid ? rule_of[la * ns + lb] : -1;
+  stuck_push<QCAP>(valid && code < 0, a, b, D, stuck, s_nstuck, s_status);
+  bool act = valid && code >= 0;
+  const int rid = act ? (code >> 1) : 0;
+  if (act && (code & 1)) {
+    int t = a; a = b; b = t;
+    t = pa0; pa0 = pb0; pb0 = t;
+    t = pa1; pa1 = pb1; pb1 = t;
+  }
+  const int *T = templ + rid * RT_WORDS;
+  const int nnew = act ? T[RT_NNEW] : 0;
+  const int nalloc = act ? T[RT_NALLOC] : 0;
+  const int nfresh = act ? T[RT_NFRESH] : 0;
+  int neq = act ? T[RT_NEQ] : 0;
+  int ta, tn;
+  const int oa = wave_scan16(nalloc, &ta);
+  const int on = wave_scan16(nfresh, &tn);
+  int ba = 0, bn = 0;
+  if (__lane_id() == 0 && (ta | tn)) {
+    ba = atomicAdd(s_agent_top, ta);
+    bn = atomicAdd(s_name_top, tn);
+  }
+  ba = first_lane_value(ba);
+  bn = first_lane_value(bn);
+  const int my_a = ba + oa, my_n = bn + on;
+  if (act && (my_a + nalloc > D.agent_cap || my_n + nfresh > D.name_cap)) {
+    *s_status = ST_ENOMEM;
+    act = false;
+    neq = 0;
+  }
+  if (act) {
+    for (int kk = 0; kk < nnew; kk++) {
+      const int slot = kk == 0 ? a : (kk == 1 ? b : my_a + kk - 2);
+      const int L = T[RT_LABEL + kk];
+      label[slot] = L;
+      const int ar = arity[L];
+      if (ar > 0) port0[slot] = resolve(T[RT_PORT + 2 * kk], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
+      if (ar > 1) port1[slot] = resolve(T[RT_PORT + 2 * kk + 1], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
+    }
+    for (int f = 0; f < nfresh; f++) bind[my_n + f] = EMPTY;
+    atomicAdd(&s_rc[rid], 1ull);
+  }
+  int loops = 0;
+  int eu[MAXEQ], ev[MAXEQ], eo[MAXEQ];
+#pragma unroll
+  for (int j = 0; j < MAXEQ; j++) {
+    eo[j] = EMPTY;
+    eu[j] = 0;
+    ev[j] = 0;
+    if (j < neq) {
+      int u = resolve(T[RT_EQ + 2 * j], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
+      int v = resolve(T[RT_EQ + 2 * j + 1], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
+      if (u >= 0) { const int t = u; u = v; v = t; }
+      eu[j] = u;
+      ev[j] = v;
+      if (u < 0 && u != v) eo[j] = xchg(&bind[~u], v);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < MAXEQ; j++) {
+    const bool has = j < neq;
+    if (ballot(has) == 0ull) break;
+    bool prod = false;
+    int ou = 0, ov = 0;
+    if (has) {
+      const int u = eu[j], v = ev[j];
+      if (u >= 0) { prod = true; ou = u; ov = v; }
+      else if (u == v) loops++;
+      else if (eo[j] != EMPTY) prod = link(eo[j], v, bind, ou, ov, loops, s_status);
+    }
+    wave_push(prod, ou, ov, nq_l, QCAP, nq_g, D.qcap, ncnt, s_status);
+  }
+  if (loops) atomicAdd(s_loops, loops);
+}
+
+// one pass with rule-uniform execution (ENGINE 2): the wave walks the
+// distinct rules present among its lanes; for each, the template is read as
+// scalars (constant cache), allocation is one mask count per group, and the
+// operand choices are scalar branches
+template <int QCAP>
+__device__ __forceinline__ void pass_uniform(INET_PASS_ARGS) {
+  const int code = valid ? rule_of[la * ns + lb] : -1;
+  stuck_push<QCAP>(valid && code < 0, a, b, D, stuck, s_nstuck, s_status);
+  const bool act = valid && code >= 0;
+  const int rid = act ? (code >> 1) : -1;
+  if (act && (code & 1)) {
+    int t = a; a = b; b = t;
+    t = pa0; pa0 = pb0; pb0 = t;
+    t = pa1; pa1 = pb1; pb1 = t;
+  }
+  int lneq = 0;
+  int eu[MAXEQ], ev[MAXEQ], eo[MAXEQ];
+#pragma unroll
+  for (int j = 0; j < MAXEQ; j++) { eu[j] = 0; ev[j] = 0; eo[j] = EMPTY; }
+  unsigned long long rem = ballot(act);
+  const int lane = __lane_id();
+  while (rem) {
+    const int lead = __builtin_ctzll(rem);
+    const int r = __builtin_amdgcn_readlane(rid, lead);
+    const bool mine = rid == r;
+    const unsigned long long gm = ballot(mine);
+    rem &= ~gm;
+    const int *__restrict__ T = g_templ + r * RT_WORDS;
+    const int nnew = T[RT_NNEW], nalloc = T[RT_NALLOC], nfresh = T[RT_NFRESH], neq = T[RT_NEQ];
+    const int cnt = __popcll(gm);
+    const int rank = count_below(gm);
+    int ba = 0, bn = 0;
+    if (lane == lead) {
+      if (nalloc) ba = atomicAdd(s_agent_top, nalloc * cnt);
+      if (nfresh) bn = atomicAdd(s_name_top, nfresh * cnt);
+      atomicAdd(&s_rc[r], (unsigned long long)cnt);
+    }
+    ba = __builtin_amdgcn_readlane(ba, lead);
+    bn = __builtin_amdgcn_readlane(bn, lead);
+    const int my_a = ba + nalloc * rank, my_n = bn + nfresh * rank;
+    bool ok = mine;
+    if (mine && (my_a + nalloc > D.agent_cap || my_n + nfresh > D.name_cap)) {
+      *s_status = ST_ENOMEM;
+      ok = false;
+    }
+    if (ok) {
+      for (int kk = 0; kk < nnew; kk++) {
+        const int slot = kk == 0 ? a : (kk == 1 ? b : my_a + kk - 2);
+        const int L = T[RT_LABEL + kk];
+        label[slot] = L;
+        const int ar = g_arity[L];
+        if (ar > 0) port0[slot] = resolve_u(T[RT_PORT + 2 * kk], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
+        if (ar > 1) port1[slot] = resolve_u(T[RT_PORT + 2 * kk + 1], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
+      }
+      for (int f = 0; f < nfresh; f++) bind[my_n + f] = EMPTY;
+      lneq = neq;
+#pragma unroll
+      for (int j = 0; j < MAXEQ; j++) {
+        if (j < neq) {
+          int u = resolve_u(T[RT_EQ + 2 * j], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
+          int v = resolve_u(T[RT_EQ + 2 * j + 1], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
+          if (u >= 0) { const int t = u; u = v; v = t; }
+          eu[j] = u;
+          ev[j] = v;
+          if (u < 0 && u != v) eo[j] = xchg(&bind[~u], v);
+        }
+      }
+    }
+  }
+  int loops = 0;
+#pragma unroll
+  for (int j = 0; j < MAXEQ; j++) {
+    const bool has = j < lneq;
+    if (ballot(has) == 0ull) break;
+    bool prod = false;
+    int ou = 0, ov = 0;
+    if (has) {
+      const int u = eu[j], v = ev[j];
+      if (u >= 0) { prod = true; ou = u; ov = v; }
+      else if (u == v) loops++;
+      else if (eo[j] != EMPTY) prod = link(eo[j], v, bind, ou, ov, loops, s_status);
+    }
+    wave_push(prod, ou, ov, nq_l, QCAP, nq_g, D.qcap, ncnt, s_status);
+  }
+  if (loops) atomicAdd(s_loops, loops);
+}
+
+template <int WG, int QCAP, int ENGINE>
 __global__ __launch_bounds__(WG) void k_reduce(const NetDesc *__restrict__ descs,
                                                const int *__restrict__ order, int n_nets,
                                                int *counter, const int *__restrict__ g_rules,
                                                int ns, int nr, unsigned max_steps, int flags) {
   extern __shared__ int s_rules[];
-  __shared__ int2 q[2][QCAP];
+  __shared__ Pair q[2][QCAP];
   __shared__ int s_cnt[3];
   __shared__ int s_net;
   __shared__ int s_agent_top, s_name_top, s_status, s_nstuck, s_loops, s_maxf;
@@ -137,6 +369,8 @@ __global__ __launch_bounds__(WG) void k_reduce(const NetDesc *__restrict__ descs
   const int *rule_of = s_rules;
   const int *templ = s_rules + ns * ns;
   const int *arity = templ + nr * RT_WORDS;
+  const int *__restrict__ g_templ = g_rules + ns * ns;
+  const int *__restrict__ g_arity = g_templ + nr * RT_WORDS;
 
   for (;;) {
     __syncthreads();
@@ -146,6 +380,13 @@ __global__ __launch_bounds__(WG) void k_reduce(const NetDesc *__restrict__ descs
     if (k >= n_nets) break;
     const NetDesc D = descs[order[k]];
     NetState *st = D.st;
+    gint *const label = (gint *)D.label;
+    gint *const port0 = (gint *)D.port0;
+    gint *const port1 = (gint *)D.port1;
+    gint *const bind = (gint *)D.bind;
+    gint2 *const queue0 = (gint2 *)D.queue0;
+    gint2 *const queue1 = (gint2 *)D.queue1;
+    gint2 *const stuck = (gint2 *)D.stuck;
     const int phase = st->phase;
     if (phase == PHASE_DONE || st->status == ST_ENOMEM || st->status == ST_EINTERNAL) continue;
     const int nfront = st->frontier;
@@ -172,19 +413,19 @@ __global__ __launch_bounds__(WG) void k_reduce(const NetDesc *__restrict__ descs
       for (int base = 0; base < nfront; base += WG) {
         const int i = base + tid;
         const bool valid = i < nfront;
-        int2 e = make_int2(0, 0);
-        if (valid) e = D.queue0[i];
+        Pair e = mkpair(0, 0);
+        if (valid) e = unpk(queue0[i]);
         int ou = 0, ov = 0, loops = 0;
-        const bool prod = valid && link(e.x, e.y, D.bind, ou, ov, loops, &s_status);
-        wave_push(prod, ou, ov, q[1], QCAP, D.queue1, D.qcap, &s_cnt[1], &s_status);
+        const bool prod = valid && link(e.x, e.y, bind, ou, ov, loops, &s_status);
+        wave_push(prod, ou, ov, q[1], QCAP, queue1, D.qcap, &s_cnt[1], &s_status);
         if (loops) atomicAdd(&s_loops, loops);
       }
       cur = 1;
       ci = 1;
     } else {
-      int2 *g = cur ? D.queue1 : D.queue0;
+      gint2 *g = cur ? queue1 : queue0;
       const int nl = nfront < QCAP ? nfront : QCAP;
-      for (int i = tid; i < nl; i += WG) q[cur][i] = g[i];
+      for (int i = tid; i < nl; i += WG) q[cur][i] = unpk(g[i]);
     }
 
     for (;;) {
@@ -197,122 +438,38 @@ __global__ __launch_bounds__(WG) void k_reduce(const NetDesc *__restrict__ descs
         s_cnt[cnn] = 0;
         if (n > s_maxf) s_maxf = n;
       }
-      const int2 *cq_l = q[cur];
-      const int2 *cq_g = cur ? D.queue1 : D.queue0;
-      int2 *nq_l = q[cur ^ 1];
-      int2 *nq_g = cur ? D.queue0 : D.queue1;
+      const Pair *cq_l = q[cur];
+      const gint2 *cq_g = cur ? queue1 : queue0;
+      Pair *nq_l = q[cur ^ 1];
+      gint2 *nq_g = cur ? queue0 : queue1;
       for (int base = 0; base < n; base += WG) {
         const int i = base + tid;
         const bool valid = i < n;
-        int2 rx = make_int2(0, 0);
-        if (valid) rx = (i < QCAP) ? cq_l[i] : cq_g[i];
-        int a = rx.x, b = rx.y;
+        Pair rx = mkpair(0, 0);
+        if (valid) {
+          if (i < QCAP) rx = cq_l[i];
+          else rx = unpk(cq_g[i]);
+        }
+        const int a = rx.x, b = rx.y;
         int la = 0, lb = 0, pa0 = 0, pa1 = 0, pb0 = 0, pb1 = 0;
         if (valid) {
-          la = D.label[a];
-          lb = D.label[b];
-          pa0 = D.port0[a];
-          pa1 = D.port1[a];
-          pb0 = D.port0[b];
-          pb1 = D.port1[b];
+          la = label[a];
+          lb = label[b];
+          pa0 = port0[a];
+          pa1 = port1[a];
+          pb0 = port0[b];
+          pb1 = port1[b];
         }
-        const int code = valid ? rule_of[la * ns + lb] : -1;
-        // active pairs without a rule stay as residual equations
-        {
-          const bool stk = valid && code < 0;
-          const unsigned long long m = ballot(stk);
-          if (m) {
-            int sb = 0;
-            if (__lane_id() == 0) sb = atomicAdd(&s_nstuck, __popcll(m));
-            sb = first_lane_value(sb);
-            if (stk) {
-              const int si = sb + count_below(m);
-              if (si < D.scap) D.stuck[si] = make_int2(a, b);
-              else s_status = ST_ENOMEM;
-            }
-          }
-        }
-        bool act = valid && code >= 0;
-        const int rid = act ? (code >> 1) : 0;
-        if (act && (code & 1)) {
-          int t = a; a = b; b = t;
-          t = pa0; pa0 = pb0; pb0 = t;
-          t = pa1; pa1 = pb1; pb1 = t;
-        }
-        const int *T = templ + rid * RT_WORDS;
-        const int nnew = act ? T[RT_NNEW] : 0;
-        const int nalloc = act ? T[RT_NALLOC] : 0;
-        const int nfresh = act ? T[RT_NFRESH] : 0;
-        int neq = act ? T[RT_NEQ] : 0;
-        // bump allocation: wave prefix sums, one LDS atomic per wave
-        int ta, tn;
-        const int oa = wave_scan16(nalloc, &ta);
-        const int on = wave_scan16(nfresh, &tn);
-        int ba = 0, bn = 0;
-        if (__lane_id() == 0 && (ta | tn)) {
-          ba = atomicAdd(&s_agent_top, ta);
-          bn = atomicAdd(&s_name_top, tn);
-        }
-        ba = first_lane_value(ba);
-        bn = first_lane_value(bn);
-        const int my_a = ba + oa, my_n = bn + on;
-        if (act && (my_a + nalloc > D.agent_cap || my_n + nfresh > D.name_cap)) {
-          s_status = ST_ENOMEM;
-          act = false;
-          neq = 0;
-        }
-        if (act) {
-          for (int kk = 0; kk < nnew; kk++) {
-            const int slot = kk == 0 ? a : (kk == 1 ? b : my_a + kk - 2);
-            const int L = T[RT_LABEL + kk];
-            D.label[slot] = L;
-            const int ar = arity[L];
-            if (ar > 0)
-              D.port0[slot] = resolve(T[RT_PORT + 2 * kk], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
-            if (ar > 1)
-              D.port1[slot] =
-                  resolve(T[RT_PORT + 2 * kk + 1], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
-          }
-          for (int f = 0; f < nfresh; f++) D.bind[my_n + f] = EMPTY;
-          atomicAdd(&s_rc[rid], 1ull);
-        }
-        // com: the first exchange of every link equation is issued before
-        // any result is awaited (independent cells), then chains continue
-        int loops = 0;
-        int eu[MAXEQ], ev[MAXEQ], eo[MAXEQ];
-#pragma unroll
-        for (int j = 0; j < MAXEQ; j++) {
-          eo[j] = EMPTY;
-          eu[j] = 0;
-          ev[j] = 0;
-          if (j < neq) {
-            int u = resolve(T[RT_EQ + 2 * j], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
-            int v = resolve(T[RT_EQ + 2 * j + 1], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
-            if (u >= 0) { const int t = u; u = v; v = t; }
-            eu[j] = u;
-            ev[j] = v;
-            if (u < 0 && u != v) eo[j] = xchg(&D.bind[~u], v);
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < MAXEQ; j++) {
-          const bool has = j < neq;
-          if (ballot(has) == 0ull) break;
-          bool prod = false;
-          int ou = 0, ov = 0;
-          if (has) {
-            const int u = eu[j], v = ev[j];
-            if (u >= 0) {                       // both sides agents
-              prod = true; ou = u; ov = v;
-            } else if (u == v) {
-              loops++;                          // x = x: closed loop
-            } else if (eo[j] != EMPTY) {        // second occurrence: old = v
-              prod = link(eo[j], v, D.bind, ou, ov, loops, &s_status);
-            }
-          }
-          wave_push(prod, ou, ov, nq_l, QCAP, nq_g, D.qcap, &s_cnt[cn], &s_status);
-        }
-        if (loops) atomicAdd(&s_loops, loops);
+        if (ENGINE == 1)
+          pass_interp<QCAP>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, label, port0, port1, bind,
+                            stuck, rule_of, templ, arity, g_templ, g_arity, ns, nq_l, nq_g,
+                            &s_cnt[cn], &s_status, &s_agent_top, &s_name_top, &s_nstuck, &s_loops,
+                            s_rc);
+        else
+          pass_uniform<QCAP>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, label, port0, port1, bind,
+                             stuck, rule_of, templ, arity, g_templ, g_arity, ns, nq_l, nq_g,
+                             &s_cnt[cn], &s_status, &s_agent_top, &s_name_top, &s_nstuck, &s_loops,
+                             s_rc);
       }
       steps++;
       cur ^= 1;
@@ -323,12 +480,13 @@ __global__ __launch_bounds__(WG) void k_reduce(const NetDesc *__restrict__ descs
     const int n_left = s_cnt[ci];
     const int status = s_status;
     if (status >= 0 && n_left > 0) {
-      int2 *g = cur ? D.queue1 : D.queue0;
+      gint2 *g = cur ? queue1 : queue0;
       const int nl = n_left < QCAP ? n_left : QCAP;
-      for (int i = tid; i < nl; i += WG) g[i] = q[cur][i];
+      for (int i = tid; i < nl; i += WG) g[i] = pk(q[cur][i].x, q[cur][i].y);
     }
+    gu64 *per_rule = (gu64 *)D.per_rule;
     for (int r = tid; r < nr; r += WG)
-      if (s_rc[r]) D.per_rule[r] += s_rc[r];
+      if (s_rc[r]) per_rule[r] += s_rc[r];
     const bool done = status >= 0 && n_left == 0;
     if (tid == 0) {
       unsigned long long tot = 0;
@@ -355,7 +513,7 @@ __global__ __launch_bounds__(WG) void k_reduce(const NetDesc *__restrict__ descs
     }
     if ((flags & FLAG_JUMP) && done) {
       __syncthreads();
-      jump_cells(D.bind, tid, s_name_top, WG);
+      jump_cells(bind, tid, s_name_top, WG);
     }
   }
 }
@@ -365,25 +523,21 @@ __global__ __launch_bounds__(256) void k_jump_grid(const NetDesc *__restrict__ d
   const NetDesc D = desc[0];
   if (D.st->phase != PHASE_DONE || D.st->status < 0) return;
   const int nn = D.st->name_top;
-  jump_cells(D.bind, blockIdx.x * 256 + threadIdx.x, nn, gridDim.x * 256);
+  jump_cells((gint *)D.bind, blockIdx.x * 256 + threadIdx.x, nn, gridDim.x * 256);
 }
 
-// restore every net to its loaded state
-__global__ __launch_bounds__(256) void k_reset(const NetDesc *__restrict__ descs, int n_nets,
-                                               const int *__restrict__ init_label,
-                                               const int *__restrict__ init_port,
-                                               const int *__restrict__ init_eq, int nr) {
-  for (int ni = blockIdx.x; ni < n_nets; ni += gridDim.x) {
-    const NetDesc D = descs[ni];
-    const int *il = init_label + D.init_agent_off;
-    const int *ip = init_port + 2 * D.init_agent_off;
-    const int *ie = init_eq + 2 * D.init_eq_off;
+// restore nets to their loaded state: all n nets, or the n listed in idx
+__global__ __launch_bounds__(256) void k_reset(const NetDesc *__restrict__ descs,
+                                               const int *__restrict__ idx, int n, int nr) {
+  for (int k = blockIdx.x; k < n; k += gridDim.x) {
+    const NetDesc D = descs[idx ? idx[k] : k];
     for (int i = threadIdx.x; i < D.n_agents0; i += 256) {
-      D.label[i] = il[i];
-      D.port0[i] = ip[2 * i];
-      D.port1[i] = ip[2 * i + 1];
+      D.label[i] = D.init_label[i];
+      D.port0[i] = D.init_port[2 * i];
+      D.port1[i] = D.init_port[2 * i + 1];
     }
-    for (int i = threadIdx.x; i < D.n_eqs0; i += 256) D.queue0[i] = make_int2(ie[2 * i], ie[2 * i + 1]);
+    gint2 *q0 = (gint2 *)D.queue0;
+    for (int i = threadIdx.x; i < D.n_eqs0; i += 256) q0[i] = pk(D.init_eq[2 * i], D.init_eq[2 * i + 1]);
     for (int i = threadIdx.x; i < D.n_names0; i += 256) D.bind[i] = EMPTY;
     for (int i = threadIdx.x; i < nr; i += 256) D.per_rule[i] = 0ull;
     if (threadIdx.x == 0) {
@@ -406,21 +560,25 @@ __global__ void k_zero(int *p, int n) {
 
 namespace {
 template <int WG, int QCAP>
-int launch_t(int grid, const NetDesc *d, const int32_t *ord, int n, int32_t *ctr, const int32_t *r,
-             int ns, int nr, uint32_t ms, int flags, hipStream_t s) {
+int launch_t(int engine, int grid, const NetDesc *d, const int32_t *ord, int n, int32_t *ctr,
+             const int32_t *r, int ns, int nr, uint32_t ms, int flags, hipStream_t s) {
   const size_t dyn = (size_t)(ns * ns + nr * RT_WORDS + ns) * 4;
-  hipLaunchKernelGGL((k_reduce<WG, QCAP>), dim3(grid), dim3(WG), dyn, s, d, ord, n, ctr, r, ns, nr,
-                     ms, flags);
+  if (engine == 1)
+    hipLaunchKernelGGL((k_reduce<WG, QCAP, 1>), dim3(grid), dim3(WG), dyn, s, d, ord, n, ctr, r, ns,
+                       nr, ms, flags);
+  else
+    hipLaunchKernelGGL((k_reduce<WG, QCAP, 2>), dim3(grid), dim3(WG), dyn, s, d, ord, n, ctr, r, ns,
+                       nr, ms, flags);
   return hipGetLastError() == hipSuccess ? INET_OK : INET_EHIP;
 }
 
 template <int WG, int QCAP>
-int occ_t(int ns, int nr, int *per_cu) {
+int occ_t(int engine, int ns, int nr, int *per_cu) {
   const size_t dyn = (size_t)(ns * ns + nr * RT_WORDS + ns) * 4;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, (k_reduce<WG, QCAP>), WG, dyn) ==
-                 hipSuccess
-             ? INET_OK
-             : INET_EHIP;
+  hipError_t e = engine == 1
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, (k_reduce<WG, QCAP, 1>), WG, dyn)
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, (k_reduce<WG, QCAP, 2>), WG, dyn);
+  return e == hipSuccess ? INET_OK : INET_EHIP;
 }
 }  // namespace
 
@@ -428,13 +586,14 @@ bool shape_supported(int wg) {
   return wg == 64 || wg == 128 || wg == 256 || wg == 512 || wg == 1024;
 }
 
-LaunchShape shape_for(int wg) {
+LaunchShape shape_for(int wg, int engine) {
+  const int e = engine == 1 ? 1 : 2;
   switch (wg) {
-    case 64: return {64, 512};
-    case 128: return {128, 1024};
-    case 256: return {256, 1024};
-    case 512: return {512, 2048};
-    default: return {1024, 4096};
+    case 64: return {64, 512, e};
+    case 128: return {128, 1024, e};
+    case 256: return {256, 1024, e};
+    case 512: return {512, 2048, e};
+    default: return {1024, 4096, e};
   }
 }
 
@@ -444,7 +603,8 @@ int launch_reduce(const LaunchShape &sh, int grid, const NetDesc *d, const int32
                   int32_t *ctr, const int32_t *r, int ns, int nr, uint32_t ms, int flags,
                   hipStream_t s) {
 #define X(W, Q) \
-  if (sh.wg == W && sh.qcap == Q) return launch_t<W, Q>(grid, d, ord, n, ctr, r, ns, nr, ms, flags, s);
+  if (sh.wg == W && sh.qcap == Q)    \
+    return launch_t<W, Q>(sh.engine, grid, d, ord, n, ctr, r, ns, nr, ms, flags, s);
   INET_SHAPES(X)
 #undef X
   return INET_EINVAL;
@@ -456,17 +616,16 @@ int max_resident(const LaunchShape &sh, int ns, int nr, int *per_cu, int *n_cu) 
   if (hipDeviceGetAttribute(n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return INET_EHIP;
 #define X(W, Q) \
-  if (sh.wg == W && sh.qcap == Q) return occ_t<W, Q>(ns, nr, per_cu);
+  if (sh.wg == W && sh.qcap == Q) return occ_t<W, Q>(sh.engine, ns, nr, per_cu);
   INET_SHAPES(X)
 #undef X
   return INET_EINVAL;
 }
 
-int launch_reset(const NetDesc *d, int n, const int32_t *il, const int32_t *ip, const int32_t *ie,
-                 int nr, hipStream_t s) {
+int launch_reset(const NetDesc *d, const int32_t *idx, int n, int nr, hipStream_t s) {
   const int grid = n < 4096 ? n : 4096;
   if (grid <= 0) return INET_OK;
-  hipLaunchKernelGGL(k_reset, dim3(grid), dim3(256), 0, s, d, n, il, ip, ie, nr);
+  hipLaunchKernelGGL(k_reset, dim3(grid), dim3(256), 0, s, d, idx, n, nr);
   return hipGetLastError() == hipSuccess ? INET_OK : INET_EHIP;
 }
 

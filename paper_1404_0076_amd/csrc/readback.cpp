@@ -12,6 +12,8 @@
 #include <cstdint>
 #include <vector>
 
+#include <hip/hip_runtime.h>
+
 #include "inet_internal.h"
 #include "runtime.h"
 
@@ -114,6 +116,23 @@ int canonical_stream(const CompiledRules &R, const int32_t *label, const int32_t
     if (!emit(H, e.r, &canon, &next, *out, stk, budget)) return INET_EINVAL;
   }
   return INET_OK;
+}
+
+int readback_net(const CompiledRules &R, const NetDesc &D, const NetState &s,
+                 const std::vector<int32_t> &iface, std::vector<int32_t> *out) {
+  const int64_t na = s.agent_top, nc = s.name_top;
+  std::vector<int32_t> label(na), p0(na), p1(na), bind(nc);
+  std::vector<int2> stuck(s.n_stuck);
+  if (na) {
+    HIPCHK(hipMemcpy(label.data(), D.label, 4 * na, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(p0.data(), D.port0, 4 * na, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(p1.data(), D.port1, 4 * na, hipMemcpyDeviceToHost));
+  }
+  if (nc) HIPCHK(hipMemcpy(bind.data(), D.bind, 4 * nc, hipMemcpyDeviceToHost));
+  if (s.n_stuck)
+    HIPCHK(hipMemcpy(stuck.data(), D.stuck, 8 * (size_t)s.n_stuck, hipMemcpyDeviceToHost));
+  return canonical_stream(R, label.data(), p0.data(), p1.data(), na, bind.data(), nc, iface, stuck,
+                          out);
 }
 
 }  // namespace inet

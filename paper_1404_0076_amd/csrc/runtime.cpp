@@ -13,31 +13,11 @@
 #include "inet_internal.h"
 #include "runtime.h"
 
-namespace inet {
-int canonical_stream(const CompiledRules &R, const int32_t *label, const int32_t *p0,
-                     const int32_t *p1, int64_t n_agents, const int32_t *bind, int64_t n_cells,
-                     const std::vector<int32_t> &iface, const std::vector<int2> &stuck,
-                     std::vector<int32_t> *out);
-}
-
 using namespace inet;
 
-#define HIPCHK(x)                                  \
-  do {                                             \
-    if ((x) != hipSuccess) return INET_EHIP;       \
-  } while (0)
-
-namespace {
-
-constexpr uint32_t kStepsPerLaunch = 1u << 24;  // bound on one launch of an unbounded reduce
-constexpr int64_t kMaxCap = 0x7ffffff0;
+namespace inet {
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
-
-struct NetPlan {
-  int64_t agent_cap, name_cap, qcap, scap;
-  size_t bytes;
-};
 
 bool plan_net(int64_t n_agents, int64_t n_eqs, int64_t n_names, int64_t agent_cap,
               int64_t name_cap, NetPlan *p) {
@@ -123,12 +103,29 @@ int validate_net(const CompiledRules &R, const int32_t *label, const int32_t *po
   return INET_OK;
 }
 
-LaunchShape effective_shape(const inet_net *h) {
-  int wg = h->cfg.wg_size;
-  if (wg <= 0) wg = h->n_nets == 1 ? 1024 : 256;
-  return shape_for(wg);
+LaunchShape effective_shape(const inet_config &cfg, int n_nets) {
+  int wg = cfg.wg_size;
+  if (wg <= 0) wg = n_nets == 1 ? 1024 : 256;
+  return shape_for(wg, cfg.engine);
 }
 
+int resident_grid(const LaunchShape &sh, const CompiledRules &R, const inet_config &cfg,
+                  int n_nets, int *grid) {
+  *grid = 1;
+  if (n_nets <= 1) return INET_OK;
+  int per_cu = 0, n_cu = 0;
+  int rc = max_resident(sh, R.ns, R.nr, &per_cu, &n_cu);
+  if (rc) return rc;
+  int resident = std::max(1, per_cu) * std::max(1, n_cu);
+  if (cfg.max_resident > 0) resident = std::min(resident, cfg.max_resident);
+  *grid = std::min(n_nets, resident);
+  return INET_OK;
+}
+
+}  // namespace inet
+
+namespace {
+LaunchShape shape_of(const inet_net *h) { return inet::effective_shape(h->cfg, h->n_nets); }
 }  // namespace
 
 extern "C" {
@@ -243,8 +240,9 @@ int inet_batch_load(const inet_rules *rules, int32_t n_nets, const int32_t *labe
     D.name_cap = (int32_t)P.name_cap;
     D.qcap = (int32_t)P.qcap;
     D.scap = (int32_t)P.scap;
-    D.init_agent_off = agent_off[i];
-    D.init_eq_off = eq_off[i];
+    D.init_label = h->d_init_label + agent_off[i];
+    D.init_port = h->d_init_port + 2 * agent_off[i];
+    D.init_eq = h->d_init_eq + 2 * eq_off[i];
     D.n_agents0 = (int32_t)(agent_off[i + 1] - agent_off[i]);
     D.n_eqs0 = (int32_t)(eq_off[i + 1] - eq_off[i]);
     D.n_names0 = n_names[i];
@@ -272,7 +270,7 @@ int inet_batch_load(const inet_rules *rules, int32_t n_nets, const int32_t *labe
   if (err == hipSuccess && E > 0)
     err = hipMemcpyAsync(h->d_init_eq, eqs.data(), 8 * (size_t)E, hipMemcpyHostToDevice, stream);
   if (err != hipSuccess) { delete h; return INET_EHIP; }
-  rc = launch_reset(h->d_descs, n_nets, h->d_init_label, h->d_init_port, h->d_init_eq, R.nr, stream);
+  rc = launch_reset(h->d_descs, nullptr, n_nets, R.nr, stream);
   if (rc == INET_OK && hipStreamSynchronize(stream) != hipSuccess) rc = INET_EHIP;
   if (rc) { delete h; return rc; }
   *out = h;
@@ -291,7 +289,7 @@ int inet_load(const inet_rules *rules, const int32_t *label, const int32_t *port
 int inet_set_config(inet_net *h, const inet_config *cfg) {
   if (!h || !cfg) return INET_EINVAL;
   if (cfg->wg_size != 0 && !shape_supported(cfg->wg_size)) return INET_EINVAL;
-  if (cfg->max_resident < 0) return INET_EINVAL;
+  if (cfg->max_resident < 0 || cfg->engine < 0 || cfg->engine > 2) return INET_EINVAL;
   h->cfg = *cfg;
   return INET_OK;
 }
@@ -299,7 +297,8 @@ int inet_set_config(inet_net *h, const inet_config *cfg) {
 int inet_get_config(const inet_net *h, inet_config *cfg) {
   if (!h || !cfg) return INET_EINVAL;
   *cfg = h->cfg;
-  cfg->wg_size = effective_shape(h).wg;
+  cfg->wg_size = shape_of(h).wg;
+  cfg->engine = shape_of(h).engine;
   return INET_OK;
 }
 
@@ -315,27 +314,17 @@ int inet_set_order(inet_net *h, const int32_t *order) {
   return INET_OK;
 }
 
-int inet_reduce_async(inet_net *h, hipStream_t stream, uint64_t max_steps) {
-  if (!h) return INET_EINVAL;
-  const LaunchShape sh = effective_shape(h);
+// the reduction of every net of a handle: clear the net counter, the
+// persistent launch, the pointer-jumping pass (events around it if timed)
+static int enqueue_reduce(inet_net *h, hipStream_t stream, uint64_t max_steps, bool timed) {
+  const LaunchShape sh = shape_of(h);
   const uint32_t ms = (max_steps == 0 || max_steps > kStepsPerLaunch) ? kStepsPerLaunch : (uint32_t)max_steps;
   int grid = 1;
-  if (h->n_nets > 1) {
-    int per_cu = 0, n_cu = 0;
-    int rc = max_resident(sh, h->rules.ns, h->rules.nr, &per_cu, &n_cu);
-    if (rc) return rc;
-    int resident = std::max(1, per_cu) * std::max(1, n_cu);
-    if (h->cfg.max_resident > 0) resident = std::min(resident, h->cfg.max_resident);
-    grid = std::min(h->n_nets, resident);
-  }
-  if (!h->ev0) {
-    HIPCHK(hipEventCreate(&h->ev0));
-    HIPCHK(hipEventCreate(&h->ev1));
-  }
-  h->results_valid = false;
-  int rc = launch_zero(h->d_counter, 1, stream);
+  int rc = resident_grid(sh, h->rules, h->cfg, h->n_nets, &grid);
   if (rc) return rc;
-  HIPCHK(hipEventRecord(h->ev0, stream));
+  rc = launch_zero(h->d_counter, 1, stream);
+  if (rc) return rc;
+  if (timed) HIPCHK(hipEventRecord(h->ev0, stream));
   const bool jump = h->cfg.jump != 0;
   const int flags = (jump && h->n_nets > 1) ? FLAG_JUMP : 0;
   rc = launch_reduce(sh, grid, h->d_descs, h->d_order, h->n_nets, h->d_counter, h->d_rules,
@@ -345,8 +334,48 @@ int inet_reduce_async(inet_net *h, hipStream_t stream, uint64_t max_steps) {
     rc = launch_jump_grid(h->d_descs, 1024, stream);
     if (rc) return rc;
   }
-  HIPCHK(hipEventRecord(h->ev1, stream));
+  if (timed) HIPCHK(hipEventRecord(h->ev1, stream));
+  return INET_OK;
+}
+
+int inet_reduce_async(inet_net *h, hipStream_t stream, uint64_t max_steps) {
+  if (!h) return INET_EINVAL;
+  if (!h->ev0) {
+    HIPCHK(hipEventCreate(&h->ev0));
+    HIPCHK(hipEventCreate(&h->ev1));
+  }
+  h->results_valid = false;
+  int rc = enqueue_reduce(h, stream, max_steps, true);
+  if (rc) return rc;
   h->timed = true;
+  return INET_OK;
+}
+
+int inet_graph_capture(inet_net *h, uint64_t max_steps) {
+  if (!h) return INET_EINVAL;
+  hipStream_t cs = nullptr;
+  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  int rc = INET_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = INET_EHIP;
+  if (rc == INET_OK) rc = launch_reset(h->d_descs, nullptr, h->n_nets, h->rules.nr, cs);
+  if (rc == INET_OK) rc = enqueue_reduce(h, cs, max_steps, false);
+  if (hipStreamEndCapture(cs, &g) != hipSuccess && rc == INET_OK) rc = INET_EHIP;
+  if (rc == INET_OK) {
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    h->graph_exec = nullptr;
+    if (hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0) != hipSuccess) rc = INET_EHIP;
+  }
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cs);
+  return rc;
+}
+
+int inet_graph_launch(inet_net *h, hipStream_t stream) {
+  if (!h || !h->graph_exec) return INET_EINVAL;
+  h->results_valid = false;
+  h->timed = false;
+  HIPCHK(hipGraphLaunch(h->graph_exec, stream));
   return INET_OK;
 }
 
@@ -406,8 +435,7 @@ int inet_reduce(inet_net *h, hipStream_t stream, uint64_t max_steps, inet_result
 int inet_reset(inet_net *h, hipStream_t stream) {
   if (!h) return INET_EINVAL;
   h->results_valid = false;
-  return launch_reset(h->d_descs, h->n_nets, h->d_init_label, h->d_init_port, h->d_init_eq,
-                      h->rules.nr, stream);
+  return launch_reset(h->d_descs, nullptr, h->n_nets, h->rules.nr, stream);
 }
 
 int inet_readback(inet_net *h, int32_t net, int32_t *buf, int64_t cap, int64_t *len) {
@@ -416,20 +444,8 @@ int inet_readback(inet_net *h, int32_t net, int32_t *buf, int64_t cap, int64_t *
   const NetState &s = h->states[net];
   if (s.status < 0 && s.status != INET_ELIMIT) return s.status;
   if (s.phase != PHASE_DONE) return INET_ELIMIT;
-  const NetDesc &D = h->descs[net];
-  const int64_t na = s.agent_top, nc = s.name_top;
-  std::vector<int32_t> label(na), p0(na), p1(na), bind(nc);
-  std::vector<int2> stuck(s.n_stuck);
-  if (na) {
-    HIPCHK(hipMemcpy(label.data(), D.label, 4 * na, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(p0.data(), D.port0, 4 * na, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(p1.data(), D.port1, 4 * na, hipMemcpyDeviceToHost));
-  }
-  if (nc) HIPCHK(hipMemcpy(bind.data(), D.bind, 4 * nc, hipMemcpyDeviceToHost));
-  if (s.n_stuck) HIPCHK(hipMemcpy(stuck.data(), D.stuck, 8 * (size_t)s.n_stuck, hipMemcpyDeviceToHost));
   std::vector<int32_t> stream;
-  int rc = canonical_stream(h->rules, label.data(), p0.data(), p1.data(), na, bind.data(), nc,
-                            h->iface[net], stuck, &stream);
+  int rc = readback_net(h->rules, h->descs[net], s, h->iface[net], &stream);
   if (rc) return rc;
   *len = (int64_t)stream.size();
   if (!buf || cap < (int64_t)stream.size()) return INET_ERANGE;
@@ -471,6 +487,7 @@ int32_t inet_num_nets(const inet_net *h) { return h ? h->n_nets : 0; }
 
 void inet_free(inet_net *h) {
   if (!h) return;
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
   delete h;

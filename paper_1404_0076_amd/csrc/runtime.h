@@ -27,10 +27,10 @@ int compile_rules(const inet_rules *r, CompiledRules *out);
 // kernel launchers (kernels.hip)
 struct LaunchShape {
   int wg;
-  int qcap;  // LDS frontier capacity per buffer
+  int qcap;    // LDS frontier capacity per buffer
+  int engine;  // 1: per-lane template interpreter, 2: rule-uniform execution
 };
-int launch_reset(const NetDesc *d_descs, int n_nets, const int32_t *init_label,
-                 const int32_t *init_port, const int32_t *init_eq, int nr, hipStream_t s);
+int launch_reset(const NetDesc *d_descs, const int32_t *d_idx, int n, int nr, hipStream_t s);
 int launch_zero(int32_t *p, int n, hipStream_t s);
 int launch_reduce(const LaunchShape &shape, int grid, const NetDesc *d_descs,
                   const int32_t *d_order, int n_nets, int32_t *d_counter, const int32_t *d_rules,
@@ -38,11 +38,40 @@ int launch_reduce(const LaunchShape &shape, int grid, const NetDesc *d_descs,
 int launch_jump_grid(const NetDesc *d_desc, int grid, hipStream_t s);
 int max_resident(const LaunchShape &shape, int ns, int nr, int *per_cu, int *n_cu);
 bool shape_supported(int wg);
-LaunchShape shape_for(int wg);
+LaunchShape shape_for(int wg, int engine);
 
 enum { FLAG_JUMP = 1 };
 
+constexpr uint32_t kStepsPerLaunch = 1u << 24;  // bound on one launch of an unbounded reduce
+constexpr int64_t kMaxCap = 0x7ffffff0;
+
+struct NetPlan {
+  int64_t agent_cap, name_cap, qcap, scap;
+  size_t bytes;
+};
+size_t al(size_t x);
+bool plan_net(int64_t n_agents, int64_t n_eqs, int64_t n_names, int64_t agent_cap, int64_t name_cap,
+              NetPlan *p);
+int validate_net(const CompiledRules &R, const int32_t *label, const int32_t *port, int64_t na,
+                 const int32_t *eql, const int32_t *eqr, int64_t ne, int32_t nn,
+                 std::vector<int32_t> *iface);
+LaunchShape effective_shape(const inet_config &cfg, int n_nets);
+int resident_grid(const LaunchShape &sh, const CompiledRules &R, const inet_config &cfg, int n_nets,
+                  int *grid);
+int canonical_stream(const CompiledRules &R, const int32_t *label, const int32_t *p0,
+                     const int32_t *p1, int64_t n_agents, const int32_t *bind, int64_t n_cells,
+                     const std::vector<int32_t> &iface, const std::vector<int2> &stuck,
+                     std::vector<int32_t> *out);
+// copy one finished net's heap to the host and write its canonical stream
+int readback_net(const CompiledRules &R, const NetDesc &D, const NetState &s,
+                 const std::vector<int32_t> &iface, std::vector<int32_t> *out);
+
 }  // namespace inet
+
+#define HIPCHK(x)                                  \
+  do {                                             \
+    if ((x) != hipSuccess) return INET_EHIP;       \
+  } while (0)
 
 struct inet_net {
   inet::CompiledRules rules;
@@ -66,8 +95,9 @@ struct inet_net {
   unsigned long long *d_per_rule = nullptr; // [n_nets][nr], contiguous
   std::vector<inet::NetState> states;     // from the last inet_results
   bool results_valid = false;
-  inet_config cfg{0, 1, 0};
+  inet_config cfg{0, 1, 0, 0};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
   bool timed = false;
   inet::NetState *h_states = nullptr;     // pinned staging
 };

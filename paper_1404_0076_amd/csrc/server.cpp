@@ -1,0 +1,369 @@
+// server.cpp -- continuous batching over the net engines.
+//
+// Nets are admitted into slots while others are being reduced: each admitted
+// net gets a region of the caller's device buffer (first-fit over free byte
+// ranges; no room -> INET_EAGAIN), its image is uploaded and reset on the
+// caller's upload stream, and from the next round on it runs with every other
+// resident net.  A round is one launch of the persistent reduction kernel
+// over the running slots with a bounded step budget; a net that is not done
+// keeps its heap and its saved frontier resident for the next round.  Finished
+// nets are harvested by polling; their slot and memory return on release.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <new>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/inet.h"
+#include "inet_internal.h"
+#include "runtime.h"
+
+using namespace inet;
+
+struct inet_server {
+  CompiledRules rules;
+  int32_t max_slots = 0;
+  char *dev = nullptr;
+  size_t dev_bytes = 0;
+  int32_t *d_rules = nullptr;
+  NetDesc *d_descs = nullptr;
+  int32_t *d_order = nullptr;
+  int32_t *d_counter = nullptr;
+  NetState *d_states = nullptr;
+  unsigned long long *d_per_rule = nullptr;
+  int32_t *d_idx = nullptr;
+  size_t arena_lo = 0, arena_hi = 0;     // byte offsets into dev
+  std::map<size_t, size_t> free_ranges;  // offset -> length
+  size_t free_bytes = 0;
+  struct Slot {
+    int state = 0;  // 0 free, 1 running, 2 finished
+    int64_t ticket = 0;
+    size_t off = 0, len = 0;
+    NetDesc desc{};
+    NetState st{};
+    std::vector<int32_t> iface;
+    std::vector<int32_t> eqs;  // interleaved equations, kept until release
+  };
+  std::vector<Slot> slots;
+  std::vector<int32_t> free_slots;
+  std::unordered_map<int64_t, int32_t> by_ticket;
+  int64_t next_ticket = 1;
+  std::vector<int32_t> running;
+  std::vector<int32_t> order_host;
+  std::vector<int32_t> finished;  // slots finished but not yet reported by poll
+  std::vector<NetState> h_states;
+  inet_config cfg{0, 1, 0, 0};
+  hipEvent_t upload_done = nullptr;
+  bool upload_pending = false;
+  bool round_in_flight = false;
+};
+
+namespace {
+
+bool take_range(inet_server *s, size_t len, size_t *off) {
+  for (auto it = s->free_ranges.begin(); it != s->free_ranges.end(); ++it) {
+    if (it->second >= len) {
+      *off = it->first;
+      const size_t rest = it->second - len;
+      const size_t at = it->first + len;
+      s->free_ranges.erase(it);
+      if (rest) s->free_ranges[at] = rest;
+      s->free_bytes -= len;
+      return true;
+    }
+  }
+  return false;
+}
+
+void give_range(inet_server *s, size_t off, size_t len) {
+  auto it = s->free_ranges.emplace(off, len).first;
+  s->free_bytes += len;
+  auto next = std::next(it);
+  if (next != s->free_ranges.end() && it->first + it->second == next->first) {
+    it->second += next->second;
+    s->free_ranges.erase(next);
+  }
+  if (it != s->free_ranges.begin()) {
+    auto prev = std::prev(it);
+    if (prev->first + prev->second == it->first) {
+      prev->second += it->second;
+      s->free_ranges.erase(it);
+    }
+  }
+}
+
+inet_server::Slot *slot_of(inet_server *s, int64_t ticket) {
+  auto it = s->by_ticket.find(ticket);
+  if (it == s->by_ticket.end()) return nullptr;
+  return &s->slots[it->second];
+}
+
+}  // namespace
+
+extern "C" {
+
+int inet_server_create(const inet_rules *rules, int32_t max_slots, void *dev, size_t dev_bytes,
+                       inet_server **out) {
+  if (!out || max_slots <= 0 || !dev) return INET_EINVAL;
+  *out = nullptr;
+  inet_server *s = new (std::nothrow) inet_server();
+  if (!s) return INET_ENOMEM;
+  int rc = compile_rules(rules, &s->rules);
+  if (rc) { delete s; return rc; }
+  const CompiledRules &R = s->rules;
+  s->max_slots = max_slots;
+  s->dev = (char *)dev;
+  s->dev_bytes = dev_bytes;
+  char *base = (char *)(((uintptr_t)dev + 255) & ~uintptr_t(255));
+  char *p = base;
+  auto take = [&](size_t bytes) { char *q = p; p += al(bytes); return q; };
+  s->d_rules = (int32_t *)take(R.blob.size() * 4);
+  s->d_descs = (NetDesc *)take(sizeof(NetDesc) * (size_t)max_slots);
+  s->d_order = (int32_t *)take(4 * (size_t)max_slots);
+  s->d_counter = (int32_t *)take(256);
+  s->d_states = (NetState *)take(sizeof(NetState) * (size_t)max_slots);
+  s->d_per_rule = (unsigned long long *)take(8 * (size_t)R.nr * (size_t)max_slots + 8);
+  s->d_idx = (int32_t *)take(4 * (size_t)max_slots);
+  if ((size_t)(p - (char *)dev) + 4096 > dev_bytes) { delete s; return INET_ENOMEM; }
+  s->arena_lo = (size_t)(p - (char *)dev);
+  s->arena_hi = dev_bytes & ~size_t(255);
+  s->free_ranges[s->arena_lo] = s->arena_hi - s->arena_lo;
+  s->free_bytes = s->arena_hi - s->arena_lo;
+  s->slots.resize(max_slots);
+  for (int32_t i = max_slots - 1; i >= 0; i--) s->free_slots.push_back(i);
+  std::vector<int32_t> idx(max_slots);
+  for (int32_t i = 0; i < max_slots; i++) idx[i] = i;
+  std::vector<NetState> zero(max_slots);
+  hipError_t e = hipMemcpy(s->d_rules, R.blob.data(), R.blob.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->d_idx, idx.data(), 4 * (size_t)max_slots, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(s->d_states, zero.data(), sizeof(NetState) * (size_t)max_slots, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->upload_done, hipEventDisableTiming);
+  if (e != hipSuccess) { delete s; return INET_EHIP; }
+  *out = s;
+  return INET_OK;
+}
+
+int inet_server_set_config(inet_server *s, const inet_config *cfg) {
+  if (!s || !cfg) return INET_EINVAL;
+  if (cfg->wg_size != 0 && !shape_supported(cfg->wg_size)) return INET_EINVAL;
+  if (cfg->max_resident < 0 || cfg->engine < 0 || cfg->engine > 2) return INET_EINVAL;
+  s->cfg = *cfg;
+  return INET_OK;
+}
+
+int inet_server_submit(inet_server *s, const int32_t *label, const int32_t *port, int32_t n_agents,
+                       const int32_t *eq_lhs, const int32_t *eq_rhs, int32_t n_eqs, int32_t n_names,
+                       int64_t agent_cap, int64_t name_cap, hipStream_t stream, int64_t *ticket) {
+  if (!s || !ticket || n_agents < 0 || n_eqs < 0 || n_names < 0) return INET_EINVAL;
+  if ((n_agents && (!label || !port)) || (n_eqs && (!eq_lhs || !eq_rhs))) return INET_EINVAL;
+  const CompiledRules &R = s->rules;
+  std::vector<int32_t> iface;
+  int rc = validate_net(R, label, port, n_agents, eq_lhs, eq_rhs, n_eqs, n_names, &iface);
+  if (rc) return rc;
+  NetPlan P;
+  if (!plan_net(n_agents, n_eqs, n_names, agent_cap, name_cap, &P)) return INET_EINVAL;
+  const size_t len = P.bytes + al(4 * (size_t)n_agents + 4) + al(8 * (size_t)n_agents + 8) +
+                     al(8 * (size_t)n_eqs + 8);
+  if (s->free_slots.empty()) return INET_EAGAIN;
+  size_t off = 0;
+  if (!take_range(s, len, &off)) return INET_EAGAIN;
+  const int32_t si = s->free_slots.back();
+  s->free_slots.pop_back();
+  inet_server::Slot &S = s->slots[si];
+  S = inet_server::Slot();
+  S.state = 1;
+  S.ticket = s->next_ticket++;
+  S.off = off;
+  S.len = len;
+  S.iface.swap(iface);
+  S.eqs.resize((size_t)2 * n_eqs + 2);
+  for (int32_t e = 0; e < n_eqs; e++) {
+    S.eqs[2 * e] = eq_lhs[e];
+    S.eqs[2 * e + 1] = eq_rhs[e];
+  }
+  char *p = s->dev + off;
+  auto take = [&](size_t bytes) { char *q = p; p += al(bytes); return q; };
+  NetDesc &D = S.desc;
+  D.label = (int32_t *)take(4 * (size_t)P.agent_cap);
+  D.port0 = (int32_t *)take(4 * (size_t)P.agent_cap);
+  D.port1 = (int32_t *)take(4 * (size_t)P.agent_cap);
+  D.bind = (int32_t *)take(4 * (size_t)P.name_cap);
+  D.queue0 = (int2 *)take(8 * (size_t)P.qcap);
+  D.queue1 = (int2 *)take(8 * (size_t)P.qcap);
+  D.stuck = (int2 *)take(8 * (size_t)P.scap);
+  int32_t *il = (int32_t *)take(4 * (size_t)n_agents + 4);
+  int32_t *ip = (int32_t *)take(8 * (size_t)n_agents + 8);
+  int32_t *ie = (int32_t *)take(8 * (size_t)n_eqs + 8);
+  D.init_label = il;
+  D.init_port = ip;
+  D.init_eq = ie;
+  D.per_rule = s->d_per_rule + (size_t)si * R.nr;
+  D.st = s->d_states + si;
+  D.agent_cap = (int32_t)P.agent_cap;
+  D.name_cap = (int32_t)P.name_cap;
+  D.qcap = (int32_t)P.qcap;
+  D.scap = (int32_t)P.scap;
+  D.n_agents0 = n_agents;
+  D.n_eqs0 = n_eqs;
+  D.n_names0 = n_names;
+  D.order = si;
+  hipError_t e = hipSuccess;
+  if (n_agents) e = hipMemcpyAsync(il, label, 4 * (size_t)n_agents, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess && n_agents)
+    e = hipMemcpyAsync(ip, port, 8 * (size_t)n_agents, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess && n_eqs)
+    e = hipMemcpyAsync(ie, S.eqs.data(), 8 * (size_t)n_eqs, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->d_descs + si, &S.desc, sizeof(NetDesc), hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return INET_EHIP;
+  rc = launch_reset(s->d_descs, s->d_idx + si, 1, R.nr, stream);
+  if (rc) return rc;
+  HIPCHK(hipEventRecord(s->upload_done, stream));
+  s->upload_pending = true;
+  s->running.push_back(si);
+  s->by_ticket[S.ticket] = si;
+  *ticket = S.ticket;
+  return INET_OK;
+}
+
+int inet_server_step(inet_server *s, hipStream_t stream, uint32_t max_steps) {
+  if (!s || max_steps == 0) return INET_EINVAL;
+  if (s->round_in_flight) return INET_EINVAL;
+  if (s->running.empty()) return INET_OK;
+  if (s->upload_pending) {
+    HIPCHK(hipStreamWaitEvent(stream, s->upload_done, 0));
+    s->upload_pending = false;
+  }
+  const int n = (int)s->running.size();
+  s->order_host = s->running;
+  HIPCHK(hipMemcpyAsync(s->d_order, s->order_host.data(), 4 * (size_t)n, hipMemcpyHostToDevice, stream));
+  const LaunchShape sh = effective_shape(s->cfg, n > 1 ? n : 2);
+  int grid = 1;
+  int rc = resident_grid(sh, s->rules, s->cfg, n, &grid);
+  if (rc) return rc;
+  rc = launch_zero(s->d_counter, 1, stream);
+  if (rc) return rc;
+  rc = launch_reduce(sh, grid, s->d_descs, s->d_order, n, s->d_counter, s->d_rules, s->rules.ns,
+                     s->rules.nr, max_steps, s->cfg.jump ? FLAG_JUMP : 0, stream);
+  if (rc) return rc;
+  s->round_in_flight = true;
+  return INET_OK;
+}
+
+int inet_server_poll(inet_server *s, hipStream_t stream, int64_t *done, int32_t cap,
+                     int32_t *n_done) {
+  if (!s || !n_done || (cap > 0 && !done)) return INET_EINVAL;
+  *n_done = 0;
+  if (s->round_in_flight) {
+    HIPCHK(hipStreamSynchronize(stream));
+    s->round_in_flight = false;
+    s->h_states.resize(s->max_slots);
+    HIPCHK(hipMemcpy(s->h_states.data(), s->d_states, sizeof(NetState) * (size_t)s->max_slots,
+                     hipMemcpyDeviceToHost));
+    // only nets that took part in the round are judged: a net admitted on
+    // another stream during the round may not have been reset yet
+    std::vector<char> in_round(s->max_slots, 0);
+    for (int32_t si : s->order_host) in_round[si] = 1;
+    std::vector<int32_t> still;
+    for (int32_t si : s->running) {
+      const NetState &st = s->h_states[si];
+      inet_server::Slot &S = s->slots[si];
+      const bool over = in_round[si] && (st.phase == PHASE_DONE || st.status == ST_ENOMEM ||
+                                         st.status == ST_EINTERNAL);
+      if (over) {
+        S.state = 2;
+        S.st = st;
+        s->finished.push_back(si);
+      } else {
+        still.push_back(si);
+      }
+    }
+    s->running.swap(still);
+  }
+  int32_t k = 0;
+  while (k < cap && !s->finished.empty()) {
+    done[k++] = s->slots[s->finished.front()].ticket;
+    s->finished.erase(s->finished.begin());
+  }
+  *n_done = k;
+  return INET_OK;
+}
+
+int inet_server_result(inet_server *s, int64_t ticket, inet_result *res, int32_t *buf, int64_t cap,
+                       int64_t *len) {
+  inet_server::Slot *S = s ? slot_of(s, ticket) : nullptr;
+  if (!S || S->state != 2) return INET_EINVAL;
+  const NetState &st = S->st;
+  if (res) {
+    res->status = st.status;
+    res->n_stuck = st.n_stuck;
+    res->interactions = st.interactions;
+    res->steps = st.steps;
+    res->agents_used = st.agent_top;
+    res->names_used = st.name_top;
+    res->max_frontier = st.max_frontier;
+    res->loops = st.loops;
+  }
+  if (!len) return st.status < 0 ? st.status : INET_OK;
+  if (st.status < 0) return st.status;
+  std::vector<int32_t> stream;
+  int rc = readback_net(s->rules, S->desc, st, S->iface, &stream);
+  if (rc) return rc;
+  *len = (int64_t)stream.size();
+  if (!buf || cap < *len) return INET_ERANGE;
+  std::memcpy(buf, stream.data(), stream.size() * 4);
+  return INET_OK;
+}
+
+int inet_server_per_rule(inet_server *s, int64_t ticket, uint64_t *counts, int32_t cap) {
+  inet_server::Slot *S = s ? slot_of(s, ticket) : nullptr;
+  if (!S || S->state != 2 || !counts || cap < s->rules.nr) return INET_EINVAL;
+  if (s->rules.nr == 0) return INET_OK;
+  HIPCHK(hipMemcpy(counts, S->desc.per_rule, 8 * (size_t)s->rules.nr, hipMemcpyDeviceToHost));
+  return INET_OK;
+}
+
+int inet_server_release(inet_server *s, int64_t ticket) {
+  if (!s) return INET_EINVAL;
+  auto it = s->by_ticket.find(ticket);
+  if (it == s->by_ticket.end()) return INET_EINVAL;
+  const int32_t si = it->second;
+  inet_server::Slot &S = s->slots[si];
+  if (S.state != 2) return INET_EINVAL;
+  give_range(s, S.off, S.len);
+  S = inet_server::Slot();
+  s->free_slots.push_back(si);
+  s->by_ticket.erase(it);
+  return INET_OK;
+}
+
+int inet_server_stats(const inet_server *s, int64_t *free_bytes, int32_t *free_slots,
+                      int32_t *running) {
+  if (!s) return INET_EINVAL;
+  if (free_bytes) *free_bytes = (int64_t)s->free_bytes;
+  if (free_slots) *free_slots = (int32_t)s->free_slots.size();
+  if (running) *running = (int32_t)s->running.size();
+  return INET_OK;
+}
+
+int inet_server_net_bytes(const inet_server *s, int32_t n_agents, int32_t n_eqs, int32_t n_names,
+                          int64_t agent_cap, int64_t name_cap, int64_t *bytes) {
+  if (!s || !bytes) return INET_EINVAL;
+  NetPlan P;
+  if (!plan_net(n_agents, n_eqs, n_names, agent_cap, name_cap, &P)) return INET_EINVAL;
+  *bytes = (int64_t)(P.bytes + al(4 * (size_t)n_agents + 4) + al(8 * (size_t)n_agents + 8) +
+                     al(8 * (size_t)n_eqs + 8));
+  return INET_OK;
+}
+
+void inet_server_free(inet_server *s) {
+  if (!s) return;
+  if (s->upload_done) (void)hipEventDestroy(s->upload_done);
+  delete s;
+}
+
+}  // extern "C"
