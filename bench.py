@@ -31,6 +31,39 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ["paper_1404_0076_amd/csrc/kernels.hip", "paper_1404_0076_amd/csrc/inet_internal.h"]
+
+
+def kernel_sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(workload_key: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken with the current kernel sources on this workload (else None)."""
+    path = os.path.join(ROOT, "profiles", "k_reduce_batch4096_hbm.txt")
+    if not os.path.exists(path):
+        return None
+    meta = {}
+    for line in open(path):
+        if line.startswith("# ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            meta[k.strip()] = v.strip()
+    if meta.get("kernel_sources_sha256") != kernel_sources_hash():
+        return None
+    if meta.get("workload_key") != workload_key:
+        return None
+    try:
+        return float(meta["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def size_batch(P, R, net_list, wg, engine=0):
     """Find exact heap needs (agents and name cells are deterministic: they
     depend only on the per-rule counts) by reducing once with growing caps."""
@@ -130,12 +163,18 @@ def main():
     ap.add_argument("--fib-n", type=int, default=27)
     ap.add_argument("--wg", type=int, default=0)
     ap.add_argument("--engine", type=int, default=0, help="0 default, 1 interpreter, 2 rule-uniform")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick engine width and variant with the autotuner (cached)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true", help="skip the single-net side measurement")
+    ap.add_argument("--print-kernel-hash", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (to scale HBM counters) and exit")
     args = ap.parse_args()
+    if args.print_kernel_hash:
+        print(kernel_sources_hash())
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(nets are independent; see DESIGN.md for how the batch would shard)", file=sys.stderr)
@@ -179,8 +218,14 @@ def main():
     log(f"sizing {len(net_list)} nets (wg {wg})")
     used_a, used_n, steps, inter = size_batch(P, R, net_list, wg, args.engine)
     order = np.argsort(-steps, kind="stable").astype(np.int32)  # longest critical path first
+    engine = args.engine
+    if args.autotune:
+        from paper_1404_0076_amd import autotune
+        best = autotune.tune(R, net_list, used_a + 64, used_n + 64, order=order)
+        wg, engine = best["wg_size"], best["engine"]
+        log(f"autotune: wg {wg} engine {engine}")
     h = P.batch_load(R, net_list, agent_caps=used_a + 64, name_caps=used_n + 64)
-    h.set_config(wg_size=wg, engine=args.engine)
+    h.set_config(wg_size=wg, engine=engine)
     h.set_order(order)
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
@@ -223,7 +268,9 @@ def main():
         "data": "synthetic", "config": dict(workload, wg_size=wg, engine=h.get_config()["engine"],
                                             interactions_per_step=total),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": counter_traffic(f"{args.workload}/{args.n_nets}/{args.seed}/wg{wg}/"
+                                                f"engine{h.get_config()['engine']}"),
                      "kernel": "k_reduce", "kernel_ms": kmean,
                      "algorithmic_bytes": alg},
         "reset_ms": float(reset_ms.mean()),

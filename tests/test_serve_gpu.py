@@ -117,3 +117,24 @@ def test_server_rejects_when_full():
         srv.release(t)
     assert srv.stats()["free_slots"] == 2
     srv.free()
+
+
+def test_autotune_picks_a_valid_shape(tmp_path):
+    from paper_1404_0076_amd import autotune
+    batch = [n for _, n in small_exprs(24, 12, 5, 50_000)]
+    refs = [oracle_run(R, n) for n in batch]
+    caps = [n.n_agents + 4 * r.interactions + 1024 for n, r in zip(batch, refs)]
+    cache = str(tmp_path / "tune.json")
+    best = autotune.tune(R, batch, caps, [4 * c for c in caps], reps=1, widths=(64, 256),
+                         cache=cache)
+    assert best["wg_size"] in (64, 256) and best["engine"] in (1, 2)
+    assert len(best["trials"]) == 4
+    again = autotune.tune(R, batch, caps, [4 * c for c in caps], cache=cache)
+    assert again["wg_size"] == best["wg_size"] and again["engine"] == best["engine"]
+    # the tuned shape still gives the oracle's results
+    h = P.batch_load(R, batch, agent_caps=caps, name_caps=[4 * c for c in caps])
+    h.set_config(wg_size=best["wg_size"], engine=best["engine"])
+    rs = h.reduce()
+    for i in range(len(batch)):
+        assert_same((rs[i], h.readback(i), h.per_rule(i)), refs[i], f"tuned net {i}")
+    h.free()
