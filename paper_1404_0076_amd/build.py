@@ -17,7 +17,9 @@ ARCH = os.environ.get("INET_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 # no packed fp32 instructions anywhere (none is needed: the path is integer)
-DEVICE = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+DEVICE = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # atomics in the kernels are already aggregated per wave by hand
+          "-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]
 
 
 def build(verbose: bool = False) -> str:

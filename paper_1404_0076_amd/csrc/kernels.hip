@@ -33,6 +33,7 @@ namespace inet {
 // then compile to global_* instructions (a flat access would also hold back
 // every wait on LDS results)
 typedef __attribute__((address_space(1))) int gint;
+typedef __attribute__((address_space(1))) char gchar;
 struct Pair {  // an equation or an active pair (POD, usable in any address space)
   int x, y;
 };
@@ -45,6 +46,9 @@ __device__ __forceinline__ Pair mkpair(int x, int y) {
 // in global memory a pair is one 64-bit word, x in the low half (the same
 // bytes as an int2 {x, y})
 typedef __attribute__((address_space(1))) unsigned long long gint2;
+__device__ __forceinline__ gint2 *at2(gint2 *base, unsigned idx) {
+  return (gint2 *)((gchar *)base + (idx << 3));
+}
 __device__ __forceinline__ unsigned long long pk(int x, int y) {
   return (unsigned long long)(unsigned)x | ((unsigned long long)(unsigned)y << 32);
 }
@@ -52,6 +56,13 @@ __device__ __forceinline__ Pair unpk(unsigned long long w) {
   return mkpair((int)(unsigned)w, (int)(unsigned)(w >> 32));
 }
 typedef __attribute__((address_space(1))) unsigned long long gu64;
+
+// element idx of a heap array as base + 32-bit byte offset (capacities stay
+// below 2^29 elements of 8 bytes), which selects the scalar-base addressing
+// form of the global instructions
+__device__ __forceinline__ gint *at(gint *base, unsigned idx) {
+  return (gint *)((gchar *)base + (idx << 2));
+}
 
 __device__ __forceinline__ int count_below(unsigned long long m) {
   return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
@@ -88,7 +99,7 @@ __device__ __forceinline__ void wave_push(bool prod, int u, int v, Pair *lds_q, 
   if (prod) {
     const int i = base + count_below(m);
     if (i < lds_cap) lds_q[i] = mkpair(u, v);
-    else if (i < qcap) g_q[i] = pk(u, v);
+    else if (i < qcap) *at2(g_q, (unsigned)i) = pk(u, v);
     else *status = ST_ENOMEM;
   }
 }
@@ -111,7 +122,7 @@ __device__ __forceinline__ bool link(int u, int v, gint *__restrict__ bind, int 
     }
     if (u == v) { loops++; return false; }  // x = x: closed loop
     if (guard > (1 << 24)) { *status = ST_EINTERNAL; return false; }
-    const int old = xchg(&bind[~u], v);
+    const int old = xchg(at(bind, (unsigned)~u), v);
     if (old == EMPTY) return false;         // first occurrence: parked
     u = old;                                // second: old = v
   }
@@ -181,7 +192,7 @@ __device__ __forceinline__ void stuck_push(bool stk, int a, int b, const NetDesc
     sb = first_lane_value(sb);
     if (stk) {
       const int si = sb + count_below(m);
-      if (si < D.scap) stuck[si] = pk(a, b);
+      if (si < D.scap) *at2(stuck, (unsigned)si) = pk(a, b);
       else *s_status = ST_ENOMEM;
     }
   }
@@ -189,7 +200,7 @@ __device__ __forceinline__ void stuck_push(bool stk, int a, int b, const NetDesc
 
 template <int QCAP>
 __device__ __forceinline__ void pass_interp(INET_PASS_ARGS) {
-  const int code = valid ? rule_of[la * ns + lb] : -1;
+  const int code = valid ? rule_of[valid ? la * ns + lb : 0] : -1;
   stuck_push<QCAP>(valid && code < 0, a, b, D, stuck, s_nstuck, s_status);
   bool act = valid && code >= 0;
   const int rid = act ? (code >> 1) : 0;
@@ -223,12 +234,12 @@ __device__ __forceinline__ void pass_interp(INET_PASS_ARGS) {
     for (int kk = 0; kk < nnew; kk++) {
       const int slot = kk == 0 ? a : (kk == 1 ? b : my_a + kk - 2);
       const int L = T[RT_LABEL + kk];
-      label[slot] = L;
+      *at(label, (unsigned)slot) = L;
       const int ar = arity[L];
-      if (ar > 0) port0[slot] = resolve(T[RT_PORT + 2 * kk], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
-      if (ar > 1) port1[slot] = resolve(T[RT_PORT + 2 * kk + 1], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
+      if (ar > 0) *at(port0, (unsigned)slot) = resolve(T[RT_PORT + 2 * kk], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
+      if (ar > 1) *at(port1, (unsigned)slot) = resolve(T[RT_PORT + 2 * kk + 1], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
     }
-    for (int f = 0; f < nfresh; f++) bind[my_n + f] = EMPTY;
+    for (int f = 0; f < nfresh; f++) *at(bind, (unsigned)(my_n + f)) = EMPTY;
     atomicAdd(&s_rc[rid], 1ull);
   }
   int loops = 0;
@@ -244,7 +255,7 @@ __device__ __forceinline__ void pass_interp(INET_PASS_ARGS) {
       if (u >= 0) { const int t = u; u = v; v = t; }
       eu[j] = u;
       ev[j] = v;
-      if (u < 0 && u != v) eo[j] = xchg(&bind[~u], v);
+      if (u < 0 && u != v) eo[j] = xchg(at(bind, (unsigned)~u), v);
     }
   }
 #pragma unroll
@@ -267,11 +278,14 @@ __device__ __forceinline__ void pass_interp(INET_PASS_ARGS) {
 // one pass with rule-uniform execution (ENGINE 2): the wave walks the
 // distinct rules present among its lanes; for each, the template is read as
 // scalars (constant cache), allocation is one mask count per group, and the
-// operand choices are scalar branches
-template <int QCAP>
+// operand choices are scalar branches.  MAXL bounds the links of any rule.
+// The common com outcome -- the exchange returns a parked agent and the other
+// side is an agent -- is decided inline; longer chains take the slow path.
+// All new active pairs of the wave are appended with one LDS atomic.
+template <int QCAP, int MAXL>
 __device__ __forceinline__ void pass_uniform(INET_PASS_ARGS) {
-  const int code = valid ? rule_of[la * ns + lb] : -1;
-  stuck_push<QCAP>(valid && code < 0, a, b, D, stuck, s_nstuck, s_status);
+  const int code = valid ? rule_of[valid ? la * ns + lb : 0] : -1;
+  if (ballot(valid && code < 0)) stuck_push<QCAP>(valid && code < 0, a, b, D, stuck, s_nstuck, s_status);
   const bool act = valid && code >= 0;
   const int rid = act ? (code >> 1) : -1;
   if (act && (code & 1)) {
@@ -280,9 +294,9 @@ __device__ __forceinline__ void pass_uniform(INET_PASS_ARGS) {
     t = pa1; pa1 = pb1; pb1 = t;
   }
   int lneq = 0;
-  int eu[MAXEQ], ev[MAXEQ], eo[MAXEQ];
+  int eu[MAXL], ev[MAXL], eo[MAXL];
 #pragma unroll
-  for (int j = 0; j < MAXEQ; j++) { eu[j] = 0; ev[j] = 0; eo[j] = EMPTY; }
+  for (int j = 0; j < MAXL; j++) { eu[j] = 0; ev[j] = 0; eo[j] = EMPTY; }
   unsigned long long rem = ballot(act);
   const int lane = __lane_id();
   while (rem) {
@@ -301,8 +315,8 @@ __device__ __forceinline__ void pass_uniform(INET_PASS_ARGS) {
       if (nfresh) bn = atomicAdd(s_name_top, nfresh * cnt);
       atomicAdd(&s_rc[r], (unsigned long long)cnt);
     }
-    ba = __builtin_amdgcn_readlane(ba, lead);
-    bn = __builtin_amdgcn_readlane(bn, lead);
+    if (nalloc) ba = __builtin_amdgcn_readlane(ba, lead);
+    if (nfresh) bn = __builtin_amdgcn_readlane(bn, lead);
     const int my_a = ba + nalloc * rank, my_n = bn + nfresh * rank;
     bool ok = mine;
     if (mine && (my_a + nalloc > D.agent_cap || my_n + nfresh > D.name_cap)) {
@@ -313,45 +327,74 @@ __device__ __forceinline__ void pass_uniform(INET_PASS_ARGS) {
       for (int kk = 0; kk < nnew; kk++) {
         const int slot = kk == 0 ? a : (kk == 1 ? b : my_a + kk - 2);
         const int L = T[RT_LABEL + kk];
-        label[slot] = L;
+        *at(label, (unsigned)slot) = L;
         const int ar = g_arity[L];
-        if (ar > 0) port0[slot] = resolve_u(T[RT_PORT + 2 * kk], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
-        if (ar > 1) port1[slot] = resolve_u(T[RT_PORT + 2 * kk + 1], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
+        if (ar > 0) *at(port0, (unsigned)slot) = resolve_u(T[RT_PORT + 2 * kk], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
+        if (ar > 1) *at(port1, (unsigned)slot) = resolve_u(T[RT_PORT + 2 * kk + 1], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
       }
-      for (int f = 0; f < nfresh; f++) bind[my_n + f] = EMPTY;
+      for (int f = 0; f < nfresh; f++) *at(bind, (unsigned)(my_n + f)) = EMPTY;
       lneq = neq;
 #pragma unroll
-      for (int j = 0; j < MAXEQ; j++) {
+      for (int j = 0; j < MAXL; j++) {
         if (j < neq) {
           int u = resolve_u(T[RT_EQ + 2 * j], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
           int v = resolve_u(T[RT_EQ + 2 * j + 1], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
           if (u >= 0) { const int t = u; u = v; v = t; }
           eu[j] = u;
           ev[j] = v;
-          if (u < 0 && u != v) eo[j] = xchg(&bind[~u], v);
+          if (u < 0 && u != v) eo[j] = xchg(at(bind, (unsigned)~u), v);
         }
       }
     }
   }
+  // decide each link: a new active pair (prod), parked, a loop, or a chain
   int loops = 0;
+  bool prod[MAXL];
+  int ou[MAXL], ov[MAXL];
 #pragma unroll
-  for (int j = 0; j < MAXEQ; j++) {
+  for (int j = 0; j < MAXL; j++) {
+    prod[j] = false;
+    ou[j] = 0;
+    ov[j] = 0;
     const bool has = j < lneq;
-    if (ballot(has) == 0ull) break;
-    bool prod = false;
-    int ou = 0, ov = 0;
+    const int u = eu[j], v = ev[j], o = eo[j];
     if (has) {
-      const int u = eu[j], v = ev[j];
-      if (u >= 0) { prod = true; ou = u; ov = v; }
+      if (u >= 0) { prod[j] = true; ou[j] = u; ov[j] = v; }
       else if (u == v) loops++;
-      else if (eo[j] != EMPTY) prod = link(eo[j], v, bind, ou, ov, loops, s_status);
+      else if (o != EMPTY && o >= 0 && v >= 0) { prod[j] = true; ou[j] = o; ov[j] = v; }
     }
-    wave_push(prod, ou, ov, nq_l, QCAP, nq_g, D.qcap, ncnt, s_status);
+    const bool chain = has && u < 0 && u != v && o != EMPTY && !(o >= 0 && v >= 0);
+    if (ballot(chain)) {
+      if (chain) prod[j] = link(o, v, bind, ou[j], ov[j], loops, s_status);
+    }
+  }
+  // append all new pairs of the wave with one LDS atomic
+  unsigned long long m[MAXL];
+  int tot = 0;
+#pragma unroll
+  for (int j = 0; j < MAXL; j++) {
+    m[j] = ballot(prod[j]);
+    tot += __popcll(m[j]);
+  }
+  if (tot) {
+    int base = 0;
+    if (lane == 0) base = atomicAdd(ncnt, tot);
+    base = first_lane_value(base);
+#pragma unroll
+    for (int j = 0; j < MAXL; j++) {
+      if (prod[j]) {
+        const int i = base + count_below(m[j]);
+        if (i < QCAP) nq_l[i] = mkpair(ou[j], ov[j]);
+        else if (i < D.qcap) *at2(nq_g, (unsigned)i) = pk(ou[j], ov[j]);
+        else *s_status = ST_ENOMEM;
+      }
+      base += __popcll(m[j]);
+    }
   }
   if (loops) atomicAdd(s_loops, loops);
 }
 
-template <int WG, int QCAP, int ENGINE>
+template <int WG, int QCAP, int ENGINE, int MAXL>
 __global__ __launch_bounds__(WG) void k_reduce(const NetDesc *__restrict__ descs,
                                                const int *__restrict__ order, int n_nets,
                                                int *counter, const int *__restrict__ g_rules,
@@ -445,28 +488,28 @@ __global__ __launch_bounds__(WG) void k_reduce(const NetDesc *__restrict__ descs
       for (int base = 0; base < n; base += WG) {
         const int i = base + tid;
         const bool valid = i < n;
+        // lanes without a pair read slot 0 (always allocated) and stay idle:
+        // the loads need no branch
         Pair rx = mkpair(0, 0);
-        if (valid) {
+        if (base + WG <= QCAP) {
+          rx = cq_l[valid ? i : 0];
+        } else if (valid) {
           if (i < QCAP) rx = cq_l[i];
-          else rx = unpk(cq_g[i]);
+          else rx = unpk(*at2((gint2 *)cq_g, (unsigned)i));
         }
+        if (!valid) rx = mkpair(0, 0);
         const int a = rx.x, b = rx.y;
-        int la = 0, lb = 0, pa0 = 0, pa1 = 0, pb0 = 0, pb1 = 0;
-        if (valid) {
-          la = label[a];
-          lb = label[b];
-          pa0 = port0[a];
-          pa1 = port1[a];
-          pb0 = port0[b];
-          pb1 = port1[b];
-        }
+        const unsigned ua = (unsigned)a, ub = (unsigned)b;
+        const int la = *at(label, ua), lb = *at(label, ub);
+        const int pa0 = *at(port0, ua), pa1 = *at(port1, ua);
+        const int pb0 = *at(port0, ub), pb1 = *at(port1, ub);
         if (ENGINE == 1)
           pass_interp<QCAP>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, label, port0, port1, bind,
                             stuck, rule_of, templ, arity, g_templ, g_arity, ns, nq_l, nq_g,
                             &s_cnt[cn], &s_status, &s_agent_top, &s_name_top, &s_nstuck, &s_loops,
                             s_rc);
         else
-          pass_uniform<QCAP>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, label, port0, port1, bind,
+          pass_uniform<QCAP, MAXL>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, label, port0, port1, bind,
                              stuck, rule_of, templ, arity, g_templ, g_arity, ns, nq_l, nq_g,
                              &s_cnt[cn], &s_status, &s_agent_top, &s_name_top, &s_nstuck, &s_loops,
                              s_rc);
@@ -559,26 +602,38 @@ __global__ void k_zero(int *p, int n) {
 // launchers
 
 namespace {
+// kernel instance for an engine and the largest link count of the rule table
+// (engine 2 is compiled for rules with at most 4 links and for the maximum)
 template <int WG, int QCAP>
-int launch_t(int engine, int grid, const NetDesc *d, const int32_t *ord, int n, int32_t *ctr,
-             const int32_t *r, int ns, int nr, uint32_t ms, int flags, hipStream_t s) {
+const void *kernel_for(int engine, int maxl) {
+  if (engine == 1) return (const void *)&k_reduce<WG, QCAP, 1, MAXEQ>;
+  if (maxl <= 4) return (const void *)&k_reduce<WG, QCAP, 2, 4>;
+  return (const void *)&k_reduce<WG, QCAP, 2, MAXEQ>;
+}
+
+template <int WG, int QCAP>
+int launch_t(int engine, int maxl, int grid, const NetDesc *d, const int32_t *ord, int n,
+             int32_t *ctr, const int32_t *r, int ns, int nr, uint32_t ms, int flags, hipStream_t s) {
   const size_t dyn = (size_t)(ns * ns + nr * RT_WORDS + ns) * 4;
   if (engine == 1)
-    hipLaunchKernelGGL((k_reduce<WG, QCAP, 1>), dim3(grid), dim3(WG), dyn, s, d, ord, n, ctr, r, ns,
-                       nr, ms, flags);
+    hipLaunchKernelGGL((k_reduce<WG, QCAP, 1, MAXEQ>), dim3(grid), dim3(WG), dyn, s, d, ord, n, ctr,
+                       r, ns, nr, ms, flags);
+  else if (maxl <= 4)
+    hipLaunchKernelGGL((k_reduce<WG, QCAP, 2, 4>), dim3(grid), dim3(WG), dyn, s, d, ord, n, ctr, r,
+                       ns, nr, ms, flags);
   else
-    hipLaunchKernelGGL((k_reduce<WG, QCAP, 2>), dim3(grid), dim3(WG), dyn, s, d, ord, n, ctr, r, ns,
-                       nr, ms, flags);
+    hipLaunchKernelGGL((k_reduce<WG, QCAP, 2, MAXEQ>), dim3(grid), dim3(WG), dyn, s, d, ord, n, ctr,
+                       r, ns, nr, ms, flags);
   return hipGetLastError() == hipSuccess ? INET_OK : INET_EHIP;
 }
 
 template <int WG, int QCAP>
-int occ_t(int engine, int ns, int nr, int *per_cu) {
+int occ_t(int engine, int maxl, int ns, int nr, int *per_cu) {
   const size_t dyn = (size_t)(ns * ns + nr * RT_WORDS + ns) * 4;
-  hipError_t e = engine == 1
-      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, (k_reduce<WG, QCAP, 1>), WG, dyn)
-      : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, (k_reduce<WG, QCAP, 2>), WG, dyn);
-  return e == hipSuccess ? INET_OK : INET_EHIP;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kernel_for<WG, QCAP>(engine, maxl),
+                                                      WG, dyn) == hipSuccess
+             ? INET_OK
+             : INET_EHIP;
 }
 }  // namespace
 
@@ -586,14 +641,14 @@ bool shape_supported(int wg) {
   return wg == 64 || wg == 128 || wg == 256 || wg == 512 || wg == 1024;
 }
 
-LaunchShape shape_for(int wg, int engine) {
+LaunchShape shape_for(int wg, int engine, int maxl) {
   const int e = engine == 1 ? 1 : 2;
   switch (wg) {
-    case 64: return {64, 512, e};
-    case 128: return {128, 1024, e};
-    case 256: return {256, 1024, e};
-    case 512: return {512, 2048, e};
-    default: return {1024, 4096, e};
+    case 64: return {64, 512, e, maxl};
+    case 128: return {128, 1024, e, maxl};
+    case 256: return {256, 1024, e, maxl};
+    case 512: return {512, 2048, e, maxl};
+    default: return {1024, 4096, e, maxl};
   }
 }
 
@@ -604,7 +659,7 @@ int launch_reduce(const LaunchShape &sh, int grid, const NetDesc *d, const int32
                   hipStream_t s) {
 #define X(W, Q) \
   if (sh.wg == W && sh.qcap == Q)    \
-    return launch_t<W, Q>(sh.engine, grid, d, ord, n, ctr, r, ns, nr, ms, flags, s);
+    return launch_t<W, Q>(sh.engine, sh.maxl, grid, d, ord, n, ctr, r, ns, nr, ms, flags, s);
   INET_SHAPES(X)
 #undef X
   return INET_EINVAL;
@@ -616,7 +671,7 @@ int max_resident(const LaunchShape &sh, int ns, int nr, int *per_cu, int *n_cu) 
   if (hipDeviceGetAttribute(n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return INET_EHIP;
 #define X(W, Q) \
-  if (sh.wg == W && sh.qcap == Q) return occ_t<W, Q>(sh.engine, ns, nr, per_cu);
+  if (sh.wg == W && sh.qcap == Q) return occ_t<W, Q>(sh.engine, sh.maxl, ns, nr, per_cu);
   INET_SHAPES(X)
 #undef X
   return INET_EINVAL;

@@ -149,6 +149,7 @@ int compile_rules(const inet_rules *r, CompiledRules *out) {
   out->templ.assign((size_t)nr * RT_WORDS, OP_NONE);
   out->bytes.assign(nr, 0);
   out->rhs_agents.assign(nr, 0);
+  out->max_links = 0;
   for (int k = 0; k < nr; k++) {
     int32_t a = r->rule_lhs[2 * k], b = r->rule_lhs[2 * k + 1];
     if (a < 0 || b < 0 || a >= ns || b >= ns || a == b) return INET_EINVAL;
@@ -241,6 +242,7 @@ int compile_rules(const inet_rules *r, CompiledRules *out) {
     R[RT_NALLOC] = n_new > 2 ? n_new - 2 : 0;
     R[RT_NFRESH] = n_fresh;
     R[RT_NEQ] = n_links;
+    out->max_links = std::max(out->max_links, n_links);
     bytes += 4 * n_fresh + 8 * n_links;
     out->bytes[k] = bytes;
   }

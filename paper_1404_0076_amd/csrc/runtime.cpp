@@ -103,10 +103,10 @@ int validate_net(const CompiledRules &R, const int32_t *label, const int32_t *po
   return INET_OK;
 }
 
-LaunchShape effective_shape(const inet_config &cfg, int n_nets) {
+LaunchShape effective_shape(const inet_config &cfg, int n_nets, const CompiledRules &R) {
   int wg = cfg.wg_size;
   if (wg <= 0) wg = n_nets == 1 ? 1024 : 256;
-  return shape_for(wg, cfg.engine);
+  return shape_for(wg, cfg.engine, R.max_links);
 }
 
 int resident_grid(const LaunchShape &sh, const CompiledRules &R, const inet_config &cfg,
@@ -125,7 +125,7 @@ int resident_grid(const LaunchShape &sh, const CompiledRules &R, const inet_conf
 }  // namespace inet
 
 namespace {
-LaunchShape shape_of(const inet_net *h) { return inet::effective_shape(h->cfg, h->n_nets); }
+LaunchShape shape_of(const inet_net *h) { return inet::effective_shape(h->cfg, h->n_nets, h->rules); }
 }  // namespace
 
 extern "C" {

@@ -20,6 +20,7 @@ struct CompiledRules {
   std::vector<int32_t> blob;        // device image: rule_of | templ | arity
   std::vector<int32_t> bytes;       // algorithmic bytes per interaction of each rule
   std::vector<int32_t> rhs_agents;  // agents in each literal right-hand side
+  int max_links = 0;                // largest link count of any compiled rule
 };
 
 int compile_rules(const inet_rules *r, CompiledRules *out);
@@ -29,6 +30,7 @@ struct LaunchShape {
   int wg;
   int qcap;    // LDS frontier capacity per buffer
   int engine;  // 1: per-lane template interpreter, 2: rule-uniform execution
+  int maxl;    // largest number of link equations of any rule
 };
 int launch_reset(const NetDesc *d_descs, const int32_t *d_idx, int n, int nr, hipStream_t s);
 int launch_zero(int32_t *p, int n, hipStream_t s);
@@ -38,12 +40,12 @@ int launch_reduce(const LaunchShape &shape, int grid, const NetDesc *d_descs,
 int launch_jump_grid(const NetDesc *d_desc, int grid, hipStream_t s);
 int max_resident(const LaunchShape &shape, int ns, int nr, int *per_cu, int *n_cu);
 bool shape_supported(int wg);
-LaunchShape shape_for(int wg, int engine);
+LaunchShape shape_for(int wg, int engine, int maxl);
 
 enum { FLAG_JUMP = 1 };
 
 constexpr uint32_t kStepsPerLaunch = 1u << 24;  // bound on one launch of an unbounded reduce
-constexpr int64_t kMaxCap = 0x7ffffff0;
+constexpr int64_t kMaxCap = (int64_t(1) << 29) - 16;  // byte offsets of 8-byte entries fit 32 bits
 
 struct NetPlan {
   int64_t agent_cap, name_cap, qcap, scap;
@@ -55,7 +57,7 @@ bool plan_net(int64_t n_agents, int64_t n_eqs, int64_t n_names, int64_t agent_ca
 int validate_net(const CompiledRules &R, const int32_t *label, const int32_t *port, int64_t na,
                  const int32_t *eql, const int32_t *eqr, int64_t ne, int32_t nn,
                  std::vector<int32_t> *iface);
-LaunchShape effective_shape(const inet_config &cfg, int n_nets);
+LaunchShape effective_shape(const inet_config &cfg, int n_nets, const CompiledRules &R);
 int resident_grid(const LaunchShape &sh, const CompiledRules &R, const inet_config &cfg, int n_nets,
                   int *grid);
 int canonical_stream(const CompiledRules &R, const int32_t *label, const int32_t *p0,

@@ -241,7 +241,7 @@ int inet_server_step(inet_server *s, hipStream_t stream, uint32_t max_steps) {
   const int n = (int)s->running.size();
   s->order_host = s->running;
   HIPCHK(hipMemcpyAsync(s->d_order, s->order_host.data(), 4 * (size_t)n, hipMemcpyHostToDevice, stream));
-  const LaunchShape sh = effective_shape(s->cfg, n > 1 ? n : 2);
+  const LaunchShape sh = effective_shape(s->cfg, n > 1 ? n : 2, s->rules);
   int grid = 1;
   int rc = resident_grid(sh, s->rules, s->cfg, n, &grid);
   if (rc) return rc;
