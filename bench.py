@@ -31,7 +31,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ["paper_1404_0076_amd/csrc/kernels.hip", "paper_1404_0076_amd/csrc/inet_internal.h"]
+KERNEL_SOURCES = ["paper_1404_0076_amd/csrc/device.h", "paper_1404_0076_amd/csrc/kernels.hip",
+                  "paper_1404_0076_amd/csrc/inet_internal.h", "paper_1404_0076_amd/csrc/jit.cpp"]
 
 
 def kernel_sources_hash() -> str:
@@ -44,24 +45,29 @@ def kernel_sources_hash() -> str:
 
 
 def counter_traffic(workload_key: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken with the current kernel sources on this workload (else None)."""
-    path = os.path.join(ROOT, "profiles", "k_reduce_batch4096_hbm.txt")
-    if not os.path.exists(path):
-        return None
-    meta = {}
-    for line in open(path):
-        if line.startswith("# ") and ":" in line:
-            k, v = line[2:].split(":", 1)
-            meta[k.strip()] = v.strip()
-    if meta.get("kernel_sources_sha256") != kernel_sources_hash():
-        return None
-    if meta.get("workload_key") != workload_key:
-        return None
-    try:
-        return float(meta["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+    """HBM bytes per launch from a committed rocprofv3 counter summary
+    (profiles/*_hbm.txt), if one was taken with the current kernel sources on
+    this workload (else None)."""
+    import glob
+    want = kernel_sources_hash()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_hbm.txt"))):
+        meta = {}
+        for line in open(path):
+            if line.startswith("# ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                meta[k.strip()] = v.strip()
+        if meta.get("kernel_sources_sha256") != want or meta.get("workload_key") != workload_key:
+            continue
+        try:
+            return float(meta["traffic_bytes_per_launch"])
+        except (KeyError, ValueError):
+            continue
+    return None
+
+
+def kernel_name(engine: int, wg: int) -> str:
+    """Name of the reduce kernel as the profiler lists it."""
+    return f"inet_static_{wg}" if engine == 3 else "k_reduce"
 
 
 def size_batch(P, R, net_list, wg, engine=0):
@@ -162,7 +168,8 @@ def main():
     ap.add_argument("--n-nets", type=int, default=4096)
     ap.add_argument("--fib-n", type=int, default=27)
     ap.add_argument("--wg", type=int, default=0)
-    ap.add_argument("--engine", type=int, default=0, help="0 default, 1 interpreter, 2 rule-uniform")
+    ap.add_argument("--engine", type=int, default=0,
+                    help="0 default, 1 interpreter, 2 rule-uniform, 3 rules compiled in at load time")
     ap.add_argument("--autotune", action="store_true",
                     help="pick engine width and variant with the autotuner (cached)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -271,7 +278,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": counter_traffic(f"{args.workload}/{args.n_nets}/{args.seed}/wg{wg}/"
                                                 f"engine{h.get_config()['engine']}"),
-                     "kernel": "k_reduce", "kernel_ms": kmean,
+                     "kernel": kernel_name(h.get_config()["engine"], wg), "kernel_ms": kmean,
                      "algorithmic_bytes": alg},
         "reset_ms": float(reset_ms.mean()),
         "max_steps_per_net": int(steps.max()),

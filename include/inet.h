@@ -121,8 +121,12 @@ typedef struct {
   int32_t wg_size;          /* lanes per net engine: 64,128,256,512,1024   */
   int32_t jump;             /* 1: compress name chains after the loop      */
   int32_t max_resident;     /* cap on simultaneously resident net engines  */
-  int32_t engine;           /* 0 default; 1 per-lane rule interpreter;
-                               2 rule-uniform execution (default)          */
+  int32_t engine;           /* 0 default (3 when the run-time compiler can
+                               build it, else 2); 1 per-lane rule-template
+                               interpreter; 2 rule-uniform execution with
+                               the templates read at run time; 3 the same
+                               with the rule table compiled into the kernel
+                               at load time (hipRTC)                       */
 } inet_config;
 
 typedef struct inet_net inet_net;
@@ -206,6 +210,13 @@ int inet_rule_bytes(const inet_net *h, int32_t *bytes, int32_t cap);
  * may be NULL; otherwise it holds cap >= n_rules words. */
 int inet_rules_check(const inet_rules *rules, int32_t *n_new, int32_t *n_fresh, int32_t *n_links,
                      int32_t *bytes, int32_t cap);
+
+/* Host only: build the engine specialised for this rule table (engine 3) for
+ * the given device architecture (e.g. "gfx950") with the run-time compiler,
+ * without a device; *code_bytes gets the code object size, log (may be NULL)
+ * the compiler's messages.  INET_ENOSYS if the compiler fails. */
+int inet_jit_build(const inet_rules *rules, const char *arch, size_t *code_bytes, char *log,
+                   size_t log_cap);
 
 int32_t inet_num_nets(const inet_net *h);
 void inet_free(inet_net *h);

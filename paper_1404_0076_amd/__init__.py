@@ -29,6 +29,7 @@ EXPORTS = [
     "inet_graph_launch", "inet_server_create", "inet_server_set_config", "inet_server_net_bytes",
     "inet_server_submit", "inet_server_step", "inet_server_poll", "inet_server_result",
     "inet_server_per_rule", "inet_server_release", "inet_server_stats", "inet_server_free",
+    "inet_jit_build",
 ]
 
 
@@ -79,6 +80,7 @@ def library():
             "inet_readback": [_P, _I32, _P, _I64, _P], "inet_per_rule": [_P, _I32, _P, _I32],
             "inet_rule_bytes": [_P, _P, _I32], "inet_num_nets": [_P],
             "inet_rules_check": [_P, _P, _P, _P, _P, _I32],
+            "inet_jit_build": [_P, ctypes.c_char_p, _P, _P, ctypes.c_size_t],
             "inet_graph_capture": [_P, _U64], "inet_graph_launch": [_P, _P],
             "inet_server_create": [_P, _I32, _P, ctypes.c_size_t, _P],
             "inet_server_set_config": [_P, _P],
@@ -172,6 +174,16 @@ def rules_check(rules) -> dict:
     if rc:
         raise InetError(rc, "inet_rules_check")
     return {k: v[: rules.n_rules] for k, v in out.items()}
+
+
+def jit_build(rules, arch: str = "gfx950"):
+    """Host-only build of the rule-specialised engine (inet_jit_build):
+    (status, code object bytes, compiler log)."""
+    R = RulesArg(rules)
+    n = ctypes.c_size_t(0)
+    log = ctypes.create_string_buffer(8192)
+    rc = library().inet_jit_build(R.ptr, arch.encode(), ctypes.byref(n), log, len(log))
+    return rc, int(n.value), log.value.decode(errors="replace")
 
 
 def _stream_handle(stream):

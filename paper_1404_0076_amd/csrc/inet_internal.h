@@ -17,12 +17,21 @@
 #ifndef INET_INTERNAL_H
 #define INET_INTERNAL_H
 
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#else
+typedef int int32_t;
+typedef unsigned int uint32_t;
+typedef long long int64_t;
+typedef unsigned long long uint64_t;
+#endif
 
 namespace inet {
 
 constexpr int32_t EMPTY = 0x7fffffff;
+constexpr int MAXRULES = 64;  // rule table limit (INET_MAX_RULES)
+enum { FLAG_JUMP = 1 };      // kernel flag: compress name chains after the loop
 
 // compiled rule template (int32 words)
 constexpr int RT_WORDS = 48;
@@ -65,9 +74,9 @@ struct NetDesc {
   int32_t *port0;
   int32_t *port1;
   int32_t *bind;
-  int2 *queue0;
-  int2 *queue1;
-  int2 *stuck;
+  unsigned long long *queue0;  // pairs as 64-bit words, x in the low half
+  unsigned long long *queue1;
+  unsigned long long *stuck;
   unsigned long long *per_rule;
   NetState *st;
   // initial image (for reset): label[n], port[n][2], equations[n_eqs][2]

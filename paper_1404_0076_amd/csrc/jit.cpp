@@ -1,0 +1,210 @@
+// jit.cpp -- load-time specialisation of the net engine for one rule table.
+//
+// The device code (device.h) is compiled with hipRTC after the compiled rule
+// templates have been written into it as constant arrays (namespace rt), so
+// each rule's right-hand side becomes straight-line code (engine 3).  One code
+// object per (rule table, device architecture) holds the kernel for every
+// engine width; it is built on first use and kept for the process.
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/inet.h"
+#include "inet_internal.h"
+#include "runtime.h"
+
+namespace inet {
+
+extern const char *const kEmbeddedDeviceH;    // device.h, embedded at build time
+extern const char *const kEmbeddedInternalH;  // inet_internal.h
+
+namespace {
+
+struct Module {
+  hipModule_t mod = nullptr;
+  std::map<int, hipFunction_t> fn;  // by engine width
+  bool failed = false;
+  std::string log;
+};
+
+std::mutex g_mu;
+std::map<std::string, Module> g_mods;
+
+const int kWidths[] = {64, 128, 256, 512, 1024};
+
+std::string source_for(const CompiledRules &R) {
+  std::ostringstream o;
+  o << "#define INET_STATIC_RULES 1\n#include \"inet_internal.h\"\n";
+  o << "namespace inet { namespace rt {\n";
+  o << "constexpr int NS = " << R.ns << ";\nconstexpr int NR = " << R.nr << ";\n";
+  const int rows = R.nr > 0 ? R.nr : 1;
+  o << "constexpr int T[" << rows << "][" << RT_WORDS << "] = {";
+  for (int k = 0; k < rows; k++) {
+    o << (k ? ",\n{" : "\n{");
+    for (int w = 0; w < RT_WORDS; w++) {
+      const int v = R.nr > 0 ? R.templ[(size_t)k * RT_WORDS + w] : 0;
+      o << (w ? "," : "") << v;
+    }
+    o << "}";
+  }
+  o << "};\nconstexpr int ARITY[" << R.ns << "] = {";
+  for (int i = 0; i < R.ns; i++) o << (i ? "," : "") << R.arity[i];
+  o << "};\n} }\n#include \"device.h\"\n";
+  const int maxl = R.max_links <= 4 ? 4 : MAXEQ;
+  for (int wg : kWidths) {
+    const LaunchShape sh = shape_for(wg, 3, R.max_links);
+    o << "extern \"C\" __global__ __launch_bounds__(" << wg << ") void inet_static_" << wg
+      << "(const inet::NetDesc *__restrict__ d, const int *__restrict__ ord, int n, int *ctr,"
+         " const int *__restrict__ r, int ns, int nr, unsigned ms, int flags) {\n"
+      << "  inet::reduce_body<" << wg << ", " << sh.qcap << ", 3, " << maxl
+      << ">(d, ord, n, ctr, r, ns, nr, ms, flags);\n}\n";
+  }
+  return o.str();
+}
+
+std::string key_for(const CompiledRules &R, const std::string &arch) {
+  // FNV-1a over the device image of the rule table
+  uint64_t h = 1469598103934665603ull;
+  for (int32_t w : R.blob) {
+    for (int b = 0; b < 4; b++) {
+      h ^= (uint64_t)((w >> (8 * b)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  }
+  char buf[64];
+  std::snprintf(buf, sizeof buf, "%016llx/", (unsigned long long)h);
+  return std::string(buf) + arch;
+}
+
+// compile the specialised engine; code object into *code (no device needed)
+int compile_code(const CompiledRules &R, const std::string &arch, std::vector<char> *code,
+                 std::string *log_out) {
+  const std::string src = source_for(R);
+  if (const char *dump = std::getenv("INET_JIT_DUMP")) {  // inspection aid
+    if (FILE *f = std::fopen(dump, "w")) {
+      std::fputs(src.c_str(), f);
+      std::fclose(f);
+    }
+  }
+  const char *headers[] = {kEmbeddedInternalH, kEmbeddedDeviceH};
+  const char *names[] = {"inet_internal.h", "device.h"};
+  hiprtcProgram prog;
+  if (hiprtcCreateProgram(&prog, src.c_str(), "inet_static.hip", 2, headers, names) !=
+      HIPRTC_SUCCESS)
+    return INET_ENOSYS;
+  const std::string archopt = "--offload-arch=" + arch;
+  std::vector<const char *> opts = {archopt.c_str(), "-O3", "-std=c++17",
+                                    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
+                                    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+  const hiprtcResult cr = hiprtcCompileProgram(prog, (int)opts.size(), opts.data());
+  size_t logn = 0;
+  hiprtcGetProgramLogSize(prog, &logn);
+  if (logn > 1) {
+    std::vector<char> log(logn + 1, 0);
+    hiprtcGetProgramLog(prog, log.data());
+    log_out->assign(log.data());
+  }
+  if (cr != HIPRTC_SUCCESS) {
+    hiprtcDestroyProgram(&prog);
+    return INET_ENOSYS;
+  }
+  size_t n = 0;
+  hiprtcGetCodeSize(prog, &n);
+  code->resize(n);
+  hiprtcGetCode(prog, code->data());
+  hiprtcDestroyProgram(&prog);
+  return INET_OK;
+}
+
+int build_module(const CompiledRules &R, const std::string &arch, Module *M) {
+  std::vector<char> code;
+  int rc = compile_code(R, arch, &code, &M->log);
+  if (rc) return rc;
+  if (hipModuleLoadData(&M->mod, code.data()) != hipSuccess) return INET_EHIP;
+  for (int wg : kWidths) {
+    hipFunction_t f = nullptr;
+    const std::string name = "inet_static_" + std::to_string(wg);
+    if (hipModuleGetFunction(&f, M->mod, name.c_str()) != hipSuccess) return INET_EHIP;
+    M->fn[wg] = f;
+  }
+  return INET_OK;
+}
+
+}  // namespace
+
+// Kernel of engine 3 for the rule table and engine width (built on first use).
+int jit_function(const CompiledRules &R, int wg, hipFunction_t *out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return INET_EHIP;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return INET_EHIP;
+  std::string arch(prop.gcnArchName);
+  const std::string key = key_for(R, arch) + "/" + std::to_string(dev);
+  std::lock_guard<std::mutex> lock(g_mu);
+  Module &M = g_mods[key];
+  if (M.failed) return INET_ENOSYS;
+  if (!M.mod) {
+    int rc = build_module(R, arch, &M);
+    if (rc) {
+      M.failed = true;
+      if (std::getenv("INET_JIT_LOG")) std::fprintf(stderr, "inet jit: %d\n%s\n", rc, M.log.c_str());
+      return rc;
+    }
+  }
+  auto it = M.fn.find(wg);
+  if (it == M.fn.end()) return INET_EINVAL;
+  *out = it->second;
+  return INET_OK;
+}
+
+int jit_launch(const CompiledRules &R, const LaunchShape &sh, int grid, const NetDesc *d,
+               const int32_t *ord, int n, int32_t *ctr, const int32_t *r, uint32_t ms, int flags,
+               hipStream_t s) {
+  hipFunction_t f = nullptr;
+  int rc = jit_function(R, sh.wg, &f);
+  if (rc) return rc;
+  int ns = R.ns, nr = R.nr;
+  void *args[] = {(void *)&d, (void *)&ord, (void *)&n, (void *)&ctr, (void *)&r,
+                  (void *)&ns, (void *)&nr, (void *)&ms, (void *)&flags};
+  const unsigned dyn = (unsigned)(ns * ns + nr * RT_WORDS + ns) * 4;
+  if (hipModuleLaunchKernel(f, grid, 1, 1, sh.wg, 1, 1, dyn, s, args, nullptr) != hipSuccess)
+    return INET_EHIP;
+  return INET_OK;
+}
+
+int jit_occupancy(const CompiledRules &R, const LaunchShape &sh, int *per_cu) {
+  hipFunction_t f = nullptr;
+  int rc = jit_function(R, sh.wg, &f);
+  if (rc) return rc;
+  const size_t dyn = (size_t)(R.ns * R.ns + R.nr * RT_WORDS + R.ns) * 4;
+  return hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, f, sh.wg, dyn) == hipSuccess
+             ? INET_OK
+             : INET_EHIP;
+}
+
+}  // namespace inet
+
+extern "C" int inet_jit_build(const inet_rules *rules, const char *arch, size_t *code_bytes,
+                              char *log, size_t log_cap) {
+  inet::CompiledRules R;
+  int rc = inet::compile_rules(rules, &R);
+  if (rc) return rc;
+  if (!arch) return INET_EINVAL;
+  std::vector<char> code;
+  std::string msg;
+  rc = inet::compile_code(R, arch, &code, &msg);
+  if (log && log_cap) {
+    std::strncpy(log, msg.c_str(), log_cap - 1);
+    log[log_cap - 1] = 0;
+  }
+  if (code_bytes) *code_bytes = code.size();
+  return rc;
+}

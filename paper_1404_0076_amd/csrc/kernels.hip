@@ -1,602 +1,12 @@
-// kernels.hip -- gfx950 kernels of the interaction-net evaluator.
-//
-// One workgroup owns one net at a time ("net engine").  The frontier of
-// active pairs lives in LDS (spilling to the net's global queue when it
-// outgrows the LDS capacity), and every memory operation on the net's heap is
-// performed at workgroup scope: a net never leaves the compute unit that is
-// reducing it, so no cross-XCD coherence traffic is ever needed.  A step is
-// the loop body of evaluate() (Section 3.6):
-//   int  -- every lane takes one active pair, looks its rule up in the LDS
-//           rule table, allocates the right-hand side's agents and names with
-//           a wave-wide prefix sum and one LDS atomic per wave (the scan-based
-//           output allocation proposed in Section 4.2), writes the new agents
-//           into the int32 SoA heap, reusing the two slots of the pair;
-//   com  -- each equation left by the rule is linked: a name side exchanges
-//           the other side into the name's cell; the lane that finds the cell
-//           already filled owns the second occurrence, forms the equation
-//           (parked value = other side) and carries on along the chain; an
-//           equation between two agents is a new active pair;
-//   compaction -- new active pairs are appended to the next frontier with a
-//           wave ballot, a mask prefix count and one LDS atomic per wave.
-// A single workgroup barrier separates consecutive steps.  After the loop,
-// name-to-name chains left in the cells (the partial com of the remark after
-// the correctness proposition of Section 3.6) are compressed by pointer
-// jumping.
+// kernels.hip -- ahead-of-time instances of the device code (device.h) and
+// their host-side launchers.
 #include <hip/hip_runtime.h>
 
+#include "device.h"
 #include "inet_internal.h"
 #include "runtime.h"
 
 namespace inet {
-
-// heap pointers as global-address-space pointers: loads, stores and atomics
-// then compile to global_* instructions (a flat access would also hold back
-// every wait on LDS results)
-typedef __attribute__((address_space(1))) int gint;
-typedef __attribute__((address_space(1))) char gchar;
-struct Pair {  // an equation or an active pair (POD, usable in any address space)
-  int x, y;
-};
-__device__ __forceinline__ Pair mkpair(int x, int y) {
-  Pair p;
-  p.x = x;
-  p.y = y;
-  return p;
-}
-// in global memory a pair is one 64-bit word, x in the low half (the same
-// bytes as an int2 {x, y})
-typedef __attribute__((address_space(1))) unsigned long long gint2;
-__device__ __forceinline__ gint2 *at2(gint2 *base, unsigned idx) {
-  return (gint2 *)((gchar *)base + (idx << 3));
-}
-__device__ __forceinline__ unsigned long long pk(int x, int y) {
-  return (unsigned long long)(unsigned)x | ((unsigned long long)(unsigned)y << 32);
-}
-__device__ __forceinline__ Pair unpk(unsigned long long w) {
-  return mkpair((int)(unsigned)w, (int)(unsigned)(w >> 32));
-}
-typedef __attribute__((address_space(1))) unsigned long long gu64;
-
-// element idx of a heap array as base + 32-bit byte offset (capacities stay
-// below 2^29 elements of 8 bytes), which selects the scalar-base addressing
-// form of the global instructions
-__device__ __forceinline__ gint *at(gint *base, unsigned idx) {
-  return (gint *)((gchar *)base + (idx << 2));
-}
-
-__device__ __forceinline__ int count_below(unsigned long long m) {
-  return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                        __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-}
-
-__device__ __forceinline__ unsigned long long ballot(bool p) { return __ballot(p ? 1 : 0); }
-
-__device__ __forceinline__ int first_lane_value(int v) {
-  return __builtin_amdgcn_readfirstlane(v);
-}
-
-// exclusive prefix sum over the wave of v in [0, 15]; every lane active
-__device__ __forceinline__ int wave_scan16(int v, int *total) {
-  int pre = 0, tot = 0;
-#pragma unroll
-  for (int bit = 0; bit < 4; bit++) {
-    const unsigned long long m = ballot((v >> bit) & 1);
-    pre += count_below(m) << bit;
-    tot += __popcll(m) << bit;
-  }
-  *total = tot;
-  return pre;
-}
-
-// append (u, v) for every lane with prod set; one LDS atomic per wave
-__device__ __forceinline__ void wave_push(bool prod, int u, int v, Pair *lds_q, int lds_cap,
-                                          gint2 *g_q, int qcap, int *cnt, int *status) {
-  const unsigned long long m = ballot(prod);
-  if (m == 0ull) return;
-  int base = 0;
-  if (__lane_id() == 0) base = atomicAdd(cnt, __popcll(m));
-  base = first_lane_value(base);
-  if (prod) {
-    const int i = base + count_below(m);
-    if (i < lds_cap) lds_q[i] = mkpair(u, v);
-    else if (i < qcap) *at2(g_q, (unsigned)i) = pk(u, v);
-    else *status = ST_ENOMEM;
-  }
-}
-
-__device__ __forceinline__ int xchg(gint *p, int v) {
-  return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-// com: resolve the equation u = v.  Returns true with (ou, ov) when it ends
-// as an equation between two agents (a new active pair).  Every exchange that
-// finds a filled cell consumes both occurrences of that name, so a chain is
-// at most as long as the number of names; the guard only turns a broken
-// invariant into an error instead of a spin.
-__device__ __forceinline__ bool link(int u, int v, gint *__restrict__ bind, int &ou, int &ov,
-                                     int &loops, int *status) {
-  for (int guard = 0;; guard++) {
-    if (u >= 0) {
-      if (v >= 0) { ou = u; ov = v; return true; }
-      const int t = u; u = v; v = t;
-    }
-    if (u == v) { loops++; return false; }  // x = x: closed loop
-    if (guard > (1 << 24)) { *status = ST_EINTERNAL; return false; }
-    const int old = xchg(at(bind, (unsigned)~u), v);
-    if (old == EMPTY) return false;         // first occurrence: parked
-    u = old;                                // second: old = v
-  }
-}
-
-__device__ __forceinline__ int resolve(int op, int a, int b, int pa0, int pa1, int pb0, int pb1,
-                                       int my_a, int my_n) {
-  const int kind = op >> 4, idx = op & 15;
-  if (kind == OP_AUX) return idx == 0 ? pa0 : (idx == 1 ? pa1 : (idx == 2 ? pb0 : pb1));
-  if (kind == OP_NEW) return idx == 0 ? a : (idx == 1 ? b : my_a + idx - 2);
-  return -1 - (my_n + idx);
-}
-
-// operand of a rule template whose code is uniform across the wave: the
-// kind/index tests become scalar branches and one move is left per lane
-__device__ __forceinline__ int resolve_u(int op, int a, int b, int pa0, int pa1, int pb0, int pb1,
-                                         int my_a, int my_n) {
-  const int kind = op >> 4, idx = op & 15;
-  if (kind == OP_AUX) {
-    if (idx == 0) return pa0;
-    if (idx == 1) return pa1;
-    if (idx == 2) return pb0;
-    return pb1;
-  }
-  if (kind == OP_NEW) {
-    if (idx == 0) return a;
-    if (idx == 1) return b;
-    return my_a + (idx - 2);
-  }
-  return -1 - (my_n + idx);
-}
-
-// pointer jumping over the cells [lo, hi) with stride: a cell whose value is
-// a name whose own cell is filled takes that cell's value (a com step)
-__device__ __forceinline__ void jump_cells(gint *__restrict__ bind, int lo, int hi, int stride) {
-  for (int x = lo; x < hi; x += stride) {
-    int v = bind[x];
-    int hops = 0;
-    while (v < 0 && hops < 64) {
-      const int y = ~v;
-      if (y == x) break;
-      const int w = bind[y];
-      if (w == EMPTY) break;
-      v = w;
-      hops++;
-    }
-    if (hops) bind[x] = v;
-  }
-}
-
-// one pass of the interaction phase with the rule template interpreted per
-// lane (ENGINE 1)
-#define INET_PASS_ARGS                                                                    \
-  bool valid, int a, int b, int la, int lb, int pa0, int pa1, int pb0, int pb1, const NetDesc &D, \
-      gint *label, gint *port0, gint *port1, gint *bind, gint2 *stuck, const int *rule_of,        \
-      const int *templ, const int *arity, const int *__restrict__ g_templ,                          \
-      const int *__restrict__ g_arity, int ns, Pair *nq_l, gint2 *nq_g, int *ncnt, int *s_status,  \
-      int *s_agent_top, int *s_name_top, int *s_nstuck, int *s_loops, unsigned long long *s_rc
-
-template <int QCAP>
-__device__ __forceinline__ void stuck_push(bool stk, int a, int b, const NetDesc &D, gint2 *stuck,
-                                           int *s_nstuck, int *s_status) {
-  const unsigned long long m = ballot(stk);
-  if (m) {
-    int sb = 0;
-    if (__lane_id() == 0) sb = atomicAdd(s_nstuck, __popcll(m));
-    sb = first_lane_value(sb);
-    if (stk) {
-      const int si = sb + count_below(m);
-      if (si < D.scap) *at2(stuck, (unsigned)si) = pk(a, b);
-      else *s_status = ST_ENOMEM;
-    }
-  }
-}
-
-template <int QCAP>
-__device__ __forceinline__ void pass_interp(INET_PASS_ARGS) {
-  const int code = valid ? rule_of[valid ? la * ns + lb : 0] : -1;
-  stuck_push<QCAP>(valid && code < 0, a, b, D, stuck, s_nstuck, s_status);
-  bool act = valid && code >= 0;
-  const int rid = act ? (code >> 1) : 0;
-  if (act && (code & 1)) {
-    int t = a; a = b; b = t;
-    t = pa0; pa0 = pb0; pb0 = t;
-    t = pa1; pa1 = pb1; pb1 = t;
-  }
-  const int *T = templ + rid * RT_WORDS;
-  const int nnew = act ? T[RT_NNEW] : 0;
-  const int nalloc = act ? T[RT_NALLOC] : 0;
-  const int nfresh = act ? T[RT_NFRESH] : 0;
-  int neq = act ? T[RT_NEQ] : 0;
-  int ta, tn;
-  const int oa = wave_scan16(nalloc, &ta);
-  const int on = wave_scan16(nfresh, &tn);
-  int ba = 0, bn = 0;
-  if (__lane_id() == 0 && (ta | tn)) {
-    ba = atomicAdd(s_agent_top, ta);
-    bn = atomicAdd(s_name_top, tn);
-  }
-  ba = first_lane_value(ba);
-  bn = first_lane_value(bn);
-  const int my_a = ba + oa, my_n = bn + on;
-  if (act && (my_a + nalloc > D.agent_cap || my_n + nfresh > D.name_cap)) {
-    *s_status = ST_ENOMEM;
-    act = false;
-    neq = 0;
-  }
-  if (act) {
-    for (int kk = 0; kk < nnew; kk++) {
-      const int slot = kk == 0 ? a : (kk == 1 ? b : my_a + kk - 2);
-      const int L = T[RT_LABEL + kk];
-      *at(label, (unsigned)slot) = L;
-      const int ar = arity[L];
-      if (ar > 0) *at(port0, (unsigned)slot) = resolve(T[RT_PORT + 2 * kk], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
-      if (ar > 1) *at(port1, (unsigned)slot) = resolve(T[RT_PORT + 2 * kk + 1], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
-    }
-    for (int f = 0; f < nfresh; f++) *at(bind, (unsigned)(my_n + f)) = EMPTY;
-    atomicAdd(&s_rc[rid], 1ull);
-  }
-  int loops = 0;
-  int eu[MAXEQ], ev[MAXEQ], eo[MAXEQ];
-#pragma unroll
-  for (int j = 0; j < MAXEQ; j++) {
-    eo[j] = EMPTY;
-    eu[j] = 0;
-    ev[j] = 0;
-    if (j < neq) {
-      int u = resolve(T[RT_EQ + 2 * j], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
-      int v = resolve(T[RT_EQ + 2 * j + 1], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
-      if (u >= 0) { const int t = u; u = v; v = t; }
-      eu[j] = u;
-      ev[j] = v;
-      if (u < 0 && u != v) eo[j] = xchg(at(bind, (unsigned)~u), v);
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < MAXEQ; j++) {
-    const bool has = j < neq;
-    if (ballot(has) == 0ull) break;
-    bool prod = false;
-    int ou = 0, ov = 0;
-    if (has) {
-      const int u = eu[j], v = ev[j];
-      if (u >= 0) { prod = true; ou = u; ov = v; }
-      else if (u == v) loops++;
-      else if (eo[j] != EMPTY) prod = link(eo[j], v, bind, ou, ov, loops, s_status);
-    }
-    wave_push(prod, ou, ov, nq_l, QCAP, nq_g, D.qcap, ncnt, s_status);
-  }
-  if (loops) atomicAdd(s_loops, loops);
-}
-
-// one pass with rule-uniform execution (ENGINE 2): the wave walks the
-// distinct rules present among its lanes; for each, the template is read as
-// scalars (constant cache), allocation is one mask count per group, and the
-// operand choices are scalar branches.  MAXL bounds the links of any rule.
-// The common com outcome -- the exchange returns a parked agent and the other
-// side is an agent -- is decided inline; longer chains take the slow path.
-// All new active pairs of the wave are appended with one LDS atomic.
-template <int QCAP, int MAXL>
-__device__ __forceinline__ void pass_uniform(INET_PASS_ARGS) {
-  const int code = valid ? rule_of[valid ? la * ns + lb : 0] : -1;
-  if (ballot(valid && code < 0)) stuck_push<QCAP>(valid && code < 0, a, b, D, stuck, s_nstuck, s_status);
-  const bool act = valid && code >= 0;
-  const int rid = act ? (code >> 1) : -1;
-  if (act && (code & 1)) {
-    int t = a; a = b; b = t;
-    t = pa0; pa0 = pb0; pb0 = t;
-    t = pa1; pa1 = pb1; pb1 = t;
-  }
-  int lneq = 0;
-  int eu[MAXL], ev[MAXL], eo[MAXL];
-#pragma unroll
-  for (int j = 0; j < MAXL; j++) { eu[j] = 0; ev[j] = 0; eo[j] = EMPTY; }
-  unsigned long long rem = ballot(act);
-  const int lane = __lane_id();
-  while (rem) {
-    const int lead = __builtin_ctzll(rem);
-    const int r = __builtin_amdgcn_readlane(rid, lead);
-    const bool mine = rid == r;
-    const unsigned long long gm = ballot(mine);
-    rem &= ~gm;
-    const int *__restrict__ T = g_templ + r * RT_WORDS;
-    const int nnew = T[RT_NNEW], nalloc = T[RT_NALLOC], nfresh = T[RT_NFRESH], neq = T[RT_NEQ];
-    const int cnt = __popcll(gm);
-    const int rank = count_below(gm);
-    int ba = 0, bn = 0;
-    if (lane == lead) {
-      if (nalloc) ba = atomicAdd(s_agent_top, nalloc * cnt);
-      if (nfresh) bn = atomicAdd(s_name_top, nfresh * cnt);
-      atomicAdd(&s_rc[r], (unsigned long long)cnt);
-    }
-    if (nalloc) ba = __builtin_amdgcn_readlane(ba, lead);
-    if (nfresh) bn = __builtin_amdgcn_readlane(bn, lead);
-    const int my_a = ba + nalloc * rank, my_n = bn + nfresh * rank;
-    bool ok = mine;
-    if (mine && (my_a + nalloc > D.agent_cap || my_n + nfresh > D.name_cap)) {
-      *s_status = ST_ENOMEM;
-      ok = false;
-    }
-    if (ok) {
-      for (int kk = 0; kk < nnew; kk++) {
-        const int slot = kk == 0 ? a : (kk == 1 ? b : my_a + kk - 2);
-        const int L = T[RT_LABEL + kk];
-        *at(label, (unsigned)slot) = L;
-        const int ar = g_arity[L];
-        if (ar > 0) *at(port0, (unsigned)slot) = resolve_u(T[RT_PORT + 2 * kk], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
-        if (ar > 1) *at(port1, (unsigned)slot) = resolve_u(T[RT_PORT + 2 * kk + 1], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
-      }
-      for (int f = 0; f < nfresh; f++) *at(bind, (unsigned)(my_n + f)) = EMPTY;
-      lneq = neq;
-#pragma unroll
-      for (int j = 0; j < MAXL; j++) {
-        if (j < neq) {
-          int u = resolve_u(T[RT_EQ + 2 * j], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
-          int v = resolve_u(T[RT_EQ + 2 * j + 1], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
-          if (u >= 0) { const int t = u; u = v; v = t; }
-          eu[j] = u;
-          ev[j] = v;
-          if (u < 0 && u != v) eo[j] = xchg(at(bind, (unsigned)~u), v);
-        }
-      }
-    }
-  }
-  // decide each link: a new active pair (prod), parked, a loop, or a chain
-  int loops = 0;
-  bool prod[MAXL];
-  int ou[MAXL], ov[MAXL];
-#pragma unroll
-  for (int j = 0; j < MAXL; j++) {
-    prod[j] = false;
-    ou[j] = 0;
-    ov[j] = 0;
-    const bool has = j < lneq;
-    const int u = eu[j], v = ev[j], o = eo[j];
-    if (has) {
-      if (u >= 0) { prod[j] = true; ou[j] = u; ov[j] = v; }
-      else if (u == v) loops++;
-      else if (o != EMPTY && o >= 0 && v >= 0) { prod[j] = true; ou[j] = o; ov[j] = v; }
-    }
-    const bool chain = has && u < 0 && u != v && o != EMPTY && !(o >= 0 && v >= 0);
-    if (ballot(chain)) {
-      if (chain) prod[j] = link(o, v, bind, ou[j], ov[j], loops, s_status);
-    }
-  }
-  // append all new pairs of the wave with one LDS atomic
-  unsigned long long m[MAXL];
-  int tot = 0;
-#pragma unroll
-  for (int j = 0; j < MAXL; j++) {
-    m[j] = ballot(prod[j]);
-    tot += __popcll(m[j]);
-  }
-  if (tot) {
-    int base = 0;
-    if (lane == 0) base = atomicAdd(ncnt, tot);
-    base = first_lane_value(base);
-#pragma unroll
-    for (int j = 0; j < MAXL; j++) {
-      if (prod[j]) {
-        const int i = base + count_below(m[j]);
-        if (i < QCAP) nq_l[i] = mkpair(ou[j], ov[j]);
-        else if (i < D.qcap) *at2(nq_g, (unsigned)i) = pk(ou[j], ov[j]);
-        else *s_status = ST_ENOMEM;
-      }
-      base += __popcll(m[j]);
-    }
-  }
-  if (loops) atomicAdd(s_loops, loops);
-}
-
-template <int WG, int QCAP, int ENGINE, int MAXL>
-__global__ __launch_bounds__(WG) void k_reduce(const NetDesc *__restrict__ descs,
-                                               const int *__restrict__ order, int n_nets,
-                                               int *counter, const int *__restrict__ g_rules,
-                                               int ns, int nr, unsigned max_steps, int flags) {
-  extern __shared__ int s_rules[];
-  __shared__ Pair q[2][QCAP];
-  __shared__ int s_cnt[3];
-  __shared__ int s_net;
-  __shared__ int s_agent_top, s_name_top, s_status, s_nstuck, s_loops, s_maxf;
-  __shared__ unsigned long long s_rc[INET_MAX_RULES];
-
-  const int tid = threadIdx.x;
-  const int nwords = ns * ns + nr * RT_WORDS + ns;
-  for (int i = tid; i < nwords; i += WG) s_rules[i] = g_rules[i];
-  const int *rule_of = s_rules;
-  const int *templ = s_rules + ns * ns;
-  const int *arity = templ + nr * RT_WORDS;
-  const int *__restrict__ g_templ = g_rules + ns * ns;
-  const int *__restrict__ g_arity = g_templ + nr * RT_WORDS;
-
-  for (;;) {
-    __syncthreads();
-    if (tid == 0) s_net = atomicAdd(counter, 1);
-    __syncthreads();
-    const int k = s_net;
-    if (k >= n_nets) break;
-    const NetDesc D = descs[order[k]];
-    NetState *st = D.st;
-    gint *const label = (gint *)D.label;
-    gint *const port0 = (gint *)D.port0;
-    gint *const port1 = (gint *)D.port1;
-    gint *const bind = (gint *)D.bind;
-    gint2 *const queue0 = (gint2 *)D.queue0;
-    gint2 *const queue1 = (gint2 *)D.queue1;
-    gint2 *const stuck = (gint2 *)D.stuck;
-    const int phase = st->phase;
-    if (phase == PHASE_DONE || st->status == ST_ENOMEM || st->status == ST_EINTERNAL) continue;
-    const int nfront = st->frontier;
-    int cur = st->parity;
-    unsigned steps = st->steps;
-    // per-launch step budget (saturating)
-    const unsigned stop = (max_steps > 0xffffffffu - steps) ? 0xffffffffu : steps + max_steps;
-    if (tid == 0) {
-      s_agent_top = st->agent_top;
-      s_name_top = st->name_top;
-      s_status = 0;
-      s_nstuck = st->n_stuck;
-      s_loops = 0;
-      s_maxf = st->max_frontier;
-      s_cnt[0] = (phase == PHASE_INIT) ? 0 : nfront;
-      s_cnt[1] = 0;
-      s_cnt[2] = 0;
-    }
-    for (int r = tid; r < nr; r += WG) s_rc[r] = 0ull;
-    int ci = 0;
-    if (phase == PHASE_INIT) {
-      // the initial equations (queue0) are linked into buffer 1 (counter 1)
-      __syncthreads();
-      for (int base = 0; base < nfront; base += WG) {
-        const int i = base + tid;
-        const bool valid = i < nfront;
-        Pair e = mkpair(0, 0);
-        if (valid) e = unpk(queue0[i]);
-        int ou = 0, ov = 0, loops = 0;
-        const bool prod = valid && link(e.x, e.y, bind, ou, ov, loops, &s_status);
-        wave_push(prod, ou, ov, q[1], QCAP, queue1, D.qcap, &s_cnt[1], &s_status);
-        if (loops) atomicAdd(&s_loops, loops);
-      }
-      cur = 1;
-      ci = 1;
-    } else {
-      gint2 *g = cur ? queue1 : queue0;
-      const int nl = nfront < QCAP ? nfront : QCAP;
-      for (int i = tid; i < nl; i += WG) q[cur][i] = unpk(g[i]);
-    }
-
-    for (;;) {
-      __syncthreads();
-      const int n = s_cnt[ci];
-      if (n == 0 || s_status < 0 || steps >= stop) break;
-      const int cn = ci == 2 ? 0 : ci + 1;
-      const int cnn = cn == 2 ? 0 : cn + 1;
-      if (tid == 0) {
-        s_cnt[cnn] = 0;
-        if (n > s_maxf) s_maxf = n;
-      }
-      const Pair *cq_l = q[cur];
-      const gint2 *cq_g = cur ? queue1 : queue0;
-      Pair *nq_l = q[cur ^ 1];
-      gint2 *nq_g = cur ? queue0 : queue1;
-      for (int base = 0; base < n; base += WG) {
-        const int i = base + tid;
-        const bool valid = i < n;
-        // lanes without a pair read slot 0 (always allocated) and stay idle:
-        // the loads need no branch
-        Pair rx = mkpair(0, 0);
-        if (base + WG <= QCAP) {
-          rx = cq_l[valid ? i : 0];
-        } else if (valid) {
-          if (i < QCAP) rx = cq_l[i];
-          else rx = unpk(*at2((gint2 *)cq_g, (unsigned)i));
-        }
-        if (!valid) rx = mkpair(0, 0);
-        const int a = rx.x, b = rx.y;
-        const unsigned ua = (unsigned)a, ub = (unsigned)b;
-        const int la = *at(label, ua), lb = *at(label, ub);
-        const int pa0 = *at(port0, ua), pa1 = *at(port1, ua);
-        const int pb0 = *at(port0, ub), pb1 = *at(port1, ub);
-        if (ENGINE == 1)
-          pass_interp<QCAP>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, label, port0, port1, bind,
-                            stuck, rule_of, templ, arity, g_templ, g_arity, ns, nq_l, nq_g,
-                            &s_cnt[cn], &s_status, &s_agent_top, &s_name_top, &s_nstuck, &s_loops,
-                            s_rc);
-        else
-          pass_uniform<QCAP, MAXL>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, label, port0, port1, bind,
-                             stuck, rule_of, templ, arity, g_templ, g_arity, ns, nq_l, nq_g,
-                             &s_cnt[cn], &s_status, &s_agent_top, &s_name_top, &s_nstuck, &s_loops,
-                             s_rc);
-      }
-      steps++;
-      cur ^= 1;
-      ci = cn;
-    }
-
-    // the loop ends right after a barrier with uniform values
-    const int n_left = s_cnt[ci];
-    const int status = s_status;
-    if (status >= 0 && n_left > 0) {
-      gint2 *g = cur ? queue1 : queue0;
-      const int nl = n_left < QCAP ? n_left : QCAP;
-      for (int i = tid; i < nl; i += WG) g[i] = pk(q[cur][i].x, q[cur][i].y);
-    }
-    gu64 *per_rule = (gu64 *)D.per_rule;
-    for (int r = tid; r < nr; r += WG)
-      if (s_rc[r]) per_rule[r] += s_rc[r];
-    const bool done = status >= 0 && n_left == 0;
-    if (tid == 0) {
-      unsigned long long tot = 0;
-      for (int r = 0; r < nr; r++) tot += s_rc[r];
-      st->interactions += tot;
-      st->steps = steps;
-      st->agent_top = s_agent_top;
-      st->name_top = s_name_top;
-      st->n_stuck = s_nstuck;
-      st->loops += s_loops;
-      st->max_frontier = s_maxf;
-      if (status < 0) {
-        st->status = status;
-      } else if (!done) {
-        st->phase = PHASE_RUN;
-        st->parity = cur;
-        st->frontier = n_left;
-        st->status = ST_ELIMIT;
-      } else {
-        st->phase = PHASE_DONE;
-        st->frontier = 0;
-        st->status = s_nstuck ? ST_STUCK : ST_OK;
-      }
-    }
-    if ((flags & FLAG_JUMP) && done) {
-      __syncthreads();
-      jump_cells(bind, tid, s_name_top, WG);
-    }
-  }
-}
-
-// pointer jumping over one net's cells with the whole grid (single big nets)
-__global__ __launch_bounds__(256) void k_jump_grid(const NetDesc *__restrict__ desc) {
-  const NetDesc D = desc[0];
-  if (D.st->phase != PHASE_DONE || D.st->status < 0) return;
-  const int nn = D.st->name_top;
-  jump_cells((gint *)D.bind, blockIdx.x * 256 + threadIdx.x, nn, gridDim.x * 256);
-}
-
-// restore nets to their loaded state: all n nets, or the n listed in idx
-__global__ __launch_bounds__(256) void k_reset(const NetDesc *__restrict__ descs,
-                                               const int *__restrict__ idx, int n, int nr) {
-  for (int k = blockIdx.x; k < n; k += gridDim.x) {
-    const NetDesc D = descs[idx ? idx[k] : k];
-    for (int i = threadIdx.x; i < D.n_agents0; i += 256) {
-      D.label[i] = D.init_label[i];
-      D.port0[i] = D.init_port[2 * i];
-      D.port1[i] = D.init_port[2 * i + 1];
-    }
-    gint2 *q0 = (gint2 *)D.queue0;
-    for (int i = threadIdx.x; i < D.n_eqs0; i += 256) q0[i] = pk(D.init_eq[2 * i], D.init_eq[2 * i + 1]);
-    for (int i = threadIdx.x; i < D.n_names0; i += 256) D.bind[i] = EMPTY;
-    for (int i = threadIdx.x; i < nr; i += 256) D.per_rule[i] = 0ull;
-    if (threadIdx.x == 0) {
-      NetState s = {};
-      s.agent_top = D.n_agents0;
-      s.name_top = D.n_names0;
-      s.frontier = D.n_eqs0;
-      s.phase = PHASE_INIT;
-      *D.st = s;
-    }
-  }
-}
-
-__global__ void k_zero(int *p, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
-}
 
 // ---------------------------------------------------------------------------
 // launchers
@@ -642,7 +52,7 @@ bool shape_supported(int wg) {
 }
 
 LaunchShape shape_for(int wg, int engine, int maxl) {
-  const int e = engine == 1 ? 1 : 2;
+  const int e = (engine == 1 || engine == 3) ? engine : 2;
   switch (wg) {
     case 64: return {64, 512, e, maxl};
     case 128: return {128, 1024, e, maxl};
@@ -654,9 +64,11 @@ LaunchShape shape_for(int wg, int engine, int maxl) {
 
 #define INET_SHAPES(X) X(64, 512) X(128, 1024) X(256, 1024) X(512, 2048) X(1024, 4096)
 
-int launch_reduce(const LaunchShape &sh, int grid, const NetDesc *d, const int32_t *ord, int n,
-                  int32_t *ctr, const int32_t *r, int ns, int nr, uint32_t ms, int flags,
+int launch_reduce(const CompiledRules &R, const LaunchShape &sh, int grid, const NetDesc *d,
+                  const int32_t *ord, int n, int32_t *ctr, const int32_t *r, uint32_t ms, int flags,
                   hipStream_t s) {
+  if (sh.engine == 3) return jit_launch(R, sh, grid, d, ord, n, ctr, r, ms, flags, s);
+  const int ns = R.ns, nr = R.nr;
 #define X(W, Q) \
   if (sh.wg == W && sh.qcap == Q)    \
     return launch_t<W, Q>(sh.engine, sh.maxl, grid, d, ord, n, ctr, r, ns, nr, ms, flags, s);
@@ -665,11 +77,13 @@ int launch_reduce(const LaunchShape &sh, int grid, const NetDesc *d, const int32
   return INET_EINVAL;
 }
 
-int max_resident(const LaunchShape &sh, int ns, int nr, int *per_cu, int *n_cu) {
+int max_resident(const CompiledRules &R, const LaunchShape &sh, int *per_cu, int *n_cu) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return INET_EHIP;
   if (hipDeviceGetAttribute(n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return INET_EHIP;
+  if (sh.engine == 3) return jit_occupancy(R, sh, per_cu);
+  const int ns = R.ns, nr = R.nr;
 #define X(W, Q) \
   if (sh.wg == W && sh.qcap == Q) return occ_t<W, Q>(sh.engine, sh.maxl, ns, nr, per_cu);
   INET_SHAPES(X)

@@ -106,7 +106,13 @@ int validate_net(const CompiledRules &R, const int32_t *label, const int32_t *po
 LaunchShape effective_shape(const inet_config &cfg, int n_nets, const CompiledRules &R) {
   int wg = cfg.wg_size;
   if (wg <= 0) wg = n_nets == 1 ? 1024 : 256;
-  return shape_for(wg, cfg.engine, R.max_links);
+  int engine = cfg.engine;
+  if (engine == 0) {
+    // the rule table compiled into the kernel when hipRTC can build it
+    hipFunction_t f = nullptr;
+    engine = jit_function(R, wg, &f) == INET_OK ? 3 : 2;
+  }
+  return shape_for(wg, engine, R.max_links);
 }
 
 int resident_grid(const LaunchShape &sh, const CompiledRules &R, const inet_config &cfg,
@@ -114,7 +120,7 @@ int resident_grid(const LaunchShape &sh, const CompiledRules &R, const inet_conf
   *grid = 1;
   if (n_nets <= 1) return INET_OK;
   int per_cu = 0, n_cu = 0;
-  int rc = max_resident(sh, R.ns, R.nr, &per_cu, &n_cu);
+  int rc = max_resident(R, sh, &per_cu, &n_cu);
   if (rc) return rc;
   int resident = std::max(1, per_cu) * std::max(1, n_cu);
   if (cfg.max_resident > 0) resident = std::min(resident, cfg.max_resident);
@@ -231,9 +237,9 @@ int inet_batch_load(const inet_rules *rules, int32_t n_nets, const int32_t *labe
     D.port0 = (int32_t *)take(4 * (size_t)P.agent_cap);
     D.port1 = (int32_t *)take(4 * (size_t)P.agent_cap);
     D.bind = (int32_t *)take(4 * (size_t)P.name_cap);
-    D.queue0 = (int2 *)take(8 * (size_t)P.qcap);
-    D.queue1 = (int2 *)take(8 * (size_t)P.qcap);
-    D.stuck = (int2 *)take(8 * (size_t)P.scap);
+    D.queue0 = (unsigned long long *)take(8 * (size_t)P.qcap);
+    D.queue1 = (unsigned long long *)take(8 * (size_t)P.qcap);
+    D.stuck = (unsigned long long *)take(8 * (size_t)P.scap);
     D.per_rule = h->d_per_rule + (size_t)i * R.nr;
     D.st = h->d_states + i;
     D.agent_cap = (int32_t)P.agent_cap;
@@ -289,7 +295,7 @@ int inet_load(const inet_rules *rules, const int32_t *label, const int32_t *port
 int inet_set_config(inet_net *h, const inet_config *cfg) {
   if (!h || !cfg) return INET_EINVAL;
   if (cfg->wg_size != 0 && !shape_supported(cfg->wg_size)) return INET_EINVAL;
-  if (cfg->max_resident < 0 || cfg->engine < 0 || cfg->engine > 2) return INET_EINVAL;
+  if (cfg->max_resident < 0 || cfg->engine < 0 || cfg->engine > 3) return INET_EINVAL;
   h->cfg = *cfg;
   return INET_OK;
 }
@@ -327,8 +333,8 @@ static int enqueue_reduce(inet_net *h, hipStream_t stream, uint64_t max_steps, b
   if (timed) HIPCHK(hipEventRecord(h->ev0, stream));
   const bool jump = h->cfg.jump != 0;
   const int flags = (jump && h->n_nets > 1) ? FLAG_JUMP : 0;
-  rc = launch_reduce(sh, grid, h->d_descs, h->d_order, h->n_nets, h->d_counter, h->d_rules,
-                     h->rules.ns, h->rules.nr, ms, flags, stream);
+  rc = launch_reduce(h->rules, sh, grid, h->d_descs, h->d_order, h->n_nets, h->d_counter,
+                     h->d_rules, ms, flags, stream);
   if (rc) return rc;
   if (jump && h->n_nets == 1) {
     rc = launch_jump_grid(h->d_descs, 1024, stream);

@@ -29,20 +29,26 @@ int compile_rules(const inet_rules *r, CompiledRules *out);
 struct LaunchShape {
   int wg;
   int qcap;    // LDS frontier capacity per buffer
-  int engine;  // 1: per-lane template interpreter, 2: rule-uniform execution
+  int engine;  // 1: per-lane template interpreter, 2: rule-uniform execution,
+               // 3: rule-uniform with the rule table compiled in (load time)
   int maxl;    // largest number of link equations of any rule
 };
 int launch_reset(const NetDesc *d_descs, const int32_t *d_idx, int n, int nr, hipStream_t s);
 int launch_zero(int32_t *p, int n, hipStream_t s);
-int launch_reduce(const LaunchShape &shape, int grid, const NetDesc *d_descs,
-                  const int32_t *d_order, int n_nets, int32_t *d_counter, const int32_t *d_rules,
-                  int ns, int nr, uint32_t max_steps, int flags, hipStream_t s);
+int launch_reduce(const CompiledRules &R, const LaunchShape &shape, int grid,
+                  const NetDesc *d_descs, const int32_t *d_order, int n_nets, int32_t *d_counter,
+                  const int32_t *d_rules, uint32_t max_steps, int flags, hipStream_t s);
 int launch_jump_grid(const NetDesc *d_desc, int grid, hipStream_t s);
-int max_resident(const LaunchShape &shape, int ns, int nr, int *per_cu, int *n_cu);
+int max_resident(const CompiledRules &R, const LaunchShape &shape, int *per_cu, int *n_cu);
+// engine 3: the rule table compiled into the kernel at load time (jit.cpp)
+int jit_function(const CompiledRules &R, int wg, hipFunction_t *out);
+int jit_launch(const CompiledRules &R, const LaunchShape &sh, int grid, const NetDesc *d,
+               const int32_t *ord, int n, int32_t *ctr, const int32_t *r, uint32_t ms, int flags,
+               hipStream_t s);
+int jit_occupancy(const CompiledRules &R, const LaunchShape &sh, int *per_cu);
 bool shape_supported(int wg);
 LaunchShape shape_for(int wg, int engine, int maxl);
 
-enum { FLAG_JUMP = 1 };
 
 constexpr uint32_t kStepsPerLaunch = 1u << 24;  // bound on one launch of an unbounded reduce
 constexpr int64_t kMaxCap = (int64_t(1) << 29) - 16;  // byte offsets of 8-byte entries fit 32 bits

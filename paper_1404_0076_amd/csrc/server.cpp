@@ -150,7 +150,7 @@ int inet_server_create(const inet_rules *rules, int32_t max_slots, void *dev, si
 int inet_server_set_config(inet_server *s, const inet_config *cfg) {
   if (!s || !cfg) return INET_EINVAL;
   if (cfg->wg_size != 0 && !shape_supported(cfg->wg_size)) return INET_EINVAL;
-  if (cfg->max_resident < 0 || cfg->engine < 0 || cfg->engine > 2) return INET_EINVAL;
+  if (cfg->max_resident < 0 || cfg->engine < 0 || cfg->engine > 3) return INET_EINVAL;
   s->cfg = *cfg;
   return INET_OK;
 }
@@ -192,9 +192,9 @@ int inet_server_submit(inet_server *s, const int32_t *label, const int32_t *port
   D.port0 = (int32_t *)take(4 * (size_t)P.agent_cap);
   D.port1 = (int32_t *)take(4 * (size_t)P.agent_cap);
   D.bind = (int32_t *)take(4 * (size_t)P.name_cap);
-  D.queue0 = (int2 *)take(8 * (size_t)P.qcap);
-  D.queue1 = (int2 *)take(8 * (size_t)P.qcap);
-  D.stuck = (int2 *)take(8 * (size_t)P.scap);
+  D.queue0 = (unsigned long long *)take(8 * (size_t)P.qcap);
+  D.queue1 = (unsigned long long *)take(8 * (size_t)P.qcap);
+  D.stuck = (unsigned long long *)take(8 * (size_t)P.scap);
   int32_t *il = (int32_t *)take(4 * (size_t)n_agents + 4);
   int32_t *ip = (int32_t *)take(8 * (size_t)n_agents + 8);
   int32_t *ie = (int32_t *)take(8 * (size_t)n_eqs + 8);
@@ -247,8 +247,8 @@ int inet_server_step(inet_server *s, hipStream_t stream, uint32_t max_steps) {
   if (rc) return rc;
   rc = launch_zero(s->d_counter, 1, stream);
   if (rc) return rc;
-  rc = launch_reduce(sh, grid, s->d_descs, s->d_order, n, s->d_counter, s->d_rules, s->rules.ns,
-                     s->rules.nr, max_steps, s->cfg.jump ? FLAG_JUMP : 0, stream);
+  rc = launch_reduce(s->rules, sh, grid, s->d_descs, s->d_order, n, s->d_counter, s->d_rules,
+                     max_steps, s->cfg.jump ? FLAG_JUMP : 0, stream);
   if (rc) return rc;
   s->round_in_flight = true;
   return INET_OK;

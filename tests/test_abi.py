@@ -109,3 +109,17 @@ def test_workspace_grows_with_caps():
     assert a < b < c
     two = P.workspace_bytes(R, [10, 10], [1, 1], [1, 1], [1000, 1000], [1000, 1000])
     assert two > a
+
+
+def test_rule_specialised_engine_builds_on_host():
+    # the engine with the rule table compiled in is built by hipRTC on the
+    # host; no device is needed to produce its code object
+    rc, nbytes, log = P.jit_build(nets.arith_rules(), "gfx950")
+    assert rc == P.OK, log
+    assert nbytes > 1000
+    # a table with a rule whose right-hand side has no equations still builds
+    sig = nets.Signature(["A", "B"], [0, 0])
+    rc, nbytes, log = P.jit_build(nets.parse_rules(sig, ["A = B ->"]), "gfx950")
+    assert rc == P.OK, log
+    rc, _, _ = P.jit_build(nets.arith_rules(), "")
+    assert rc == P.ENOSYS
