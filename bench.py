@@ -159,7 +159,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="batch", choices=["batch", "mul", "fib", "addtree", "serve"])
+    ap.add_argument("--workload", default="batch",
+                    choices=["batch", "mul", "fib", "addtree", "serve", "ackermann", "algae"])
+    ap.add_argument("--ack-m", type=int, default=3)
+    ap.add_argument("--ack-n", type=int, default=7)
+    ap.add_argument("--algae-n", type=int, default=27)
     ap.add_argument("--rate", type=float, default=1.0e4, help="serve: Poisson arrival rate (nets/s)")
     ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals")
     ap.add_argument("--pool", type=int, default=8192, help="serve: request pool size")
@@ -175,6 +179,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true", help="skip the single-net side measurement")
+    ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay measurement")
     ap.add_argument("--print-kernel-hash", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (to scale HBM counters) and exit")
@@ -203,6 +208,10 @@ def main():
         print(json.dumps({"copy_bytes": args.copy_calibration, "reps": 3}), flush=True)
         return
     R = nets.arith_rules()
+    if args.workload == "ackermann":
+        R = nets.ackermann_rules()
+    elif args.workload == "algae":
+        R = nets.algae_rules()
     if args.workload == "serve":
         return bench_serve(args, P, R, nets, torch)
     if args.workload == "batch":
@@ -217,6 +226,14 @@ def main():
     elif args.workload == "fib":
         net_list = [nets.config3_fib(args.fib_n)]
         workload = {"workload": f"single net Fib(S^{args.fib_n} Z)"}
+    elif args.workload == "ackermann":
+        net_list = [nets.ackermann_net(args.ack_m, args.ack_n)]
+        workload = {"workload": f"single net Ackermann({args.ack_m},{args.ack_n}) "
+                                f"(benchmark program of Section 4.1, our rules)"}
+    elif args.workload == "algae":
+        net_list = [nets.algae_net(args.algae_n)]
+        workload = {"workload": f"single net algae L-System, generation {args.algae_n} "
+                                f"(benchmark program of Section 4.1, our rules)"}
     else:
         net_list = [nets.config1_add_tree(args.seed)]
         workload = {"workload": f"single net: balanced Add tree over 1024 numerals in [0,256), "
@@ -267,6 +284,7 @@ def main():
     for i in range(len(net_list)):
         alg += float(np.dot(h.per_rule(i).astype(np.float64), rb))
     kmean = float(kern_ms.mean())
+    wkey = f"{args.workload}/{args.n_nets}/{args.seed}/wg{wg}/engine{h.get_config()['engine']}"
     achieved = alg / (kmean * 1e-3) / 1e9
     out = {
         "metric": METRIC, "value": value, "unit": "interactions/s", "n_gpus": 1,
@@ -276,13 +294,26 @@ def main():
                                             interactions_per_step=total),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": counter_traffic(f"{args.workload}/{args.n_nets}/{args.seed}/wg{wg}/"
-                                                f"engine{h.get_config()['engine']}"),
+                     "traffic": counter_traffic(wkey),
                      "kernel": kernel_name(h.get_config()["engine"], wg), "kernel_ms": kmean,
-                     "algorithmic_bytes": alg},
+                     "algorithmic_bytes": alg, "workload_key": wkey},
         "reset_ms": float(reset_ms.mean()),
         "max_steps_per_net": int(steps.max()),
     }
+    if not args.no_graph:
+        # the same step (restore + reduce + jump) captured once as a HIP graph
+        # and replayed: the whole batch as one graph launch per step
+        h.graph_capture()
+        h.graph_launch(stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            h.graph_launch(stream)
+        torch.cuda.synchronize()
+        gwall = time.perf_counter() - t0
+        gtot = int(sum(r.interactions for r in h.results()))
+        assert gtot == total, "graph replay changed the interaction count"
+        out["graph"] = {"value": gtot * args.steps / gwall, "ms_per_step": gwall * 1e3 / args.steps}
     h.free()
     if args.workload == "batch" and not args.no_single:
         # the plain single-net evaluator on the same GPU, for the comparison

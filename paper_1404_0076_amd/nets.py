@@ -229,6 +229,45 @@ def add_rules() -> RuleTable:
     return parse_rules(ARITH_SIG, ADD_RULE_TEXTS)
 
 
+# The benchmark programs of Section 4.1 (Ackermann, an L-System), written in
+# the same style; the paper does not print its encodings, so these are ours.
+#
+# Ackermann: A(n, r) with its principal port on the first argument m;
+# A2(p, r) holds the predecessor p of m while the second argument is examined.
+#   A(0, n) = n + 1;  A(m+1, 0) = A(m, 1);  A(m+1, n+1) = A(m, A(m+1, n)).
+ACK_SIG = Signature(names=["Z", "S", "Dup", "A", "A2"], arity=[0, 1, 2, 2, 2])
+ACK_RULE_TEXTS = [
+    "A(n,r) = Z -> r = S(n)",
+    "A(n,r) = S(p) -> A2(p,r) = n",
+    "A2(p,r) = Z -> A(S(Z),r) = p",
+    "A2(p,r) = S(q) -> Dup(p1,p2) = p, A(q,t) = S(p1), A(t,r) = p2",
+    "Dup(a,b) = S(x) -> a = S(x1), b = S(x2), Dup(x1,x2) = x",
+    "Dup(a,b) = Z -> a = Z, b = Z",
+]
+
+# Algae L-System (A -> AB, B -> A): GA(r) / GB(r) expand symbol A / B for the
+# number of generations on their principal port; Cat joins two strings and
+# La / Lb are the letters of the final generation.
+ALGAE_SIG = Signature(names=["Z", "S", "Dup", "GA", "GB", "Cat", "La", "Lb"],
+                      arity=[0, 1, 2, 1, 1, 2, 0, 0])
+ALGAE_RULE_TEXTS = [
+    "GA(r) = Z -> r = La",
+    "GA(r) = S(k) -> Dup(k1,k2) = k, r = Cat(x,y), GA(x) = k1, GB(y) = k2",
+    "GB(r) = Z -> r = Lb",
+    "GB(r) = S(k) -> GA(r) = k",
+    "Dup(a,b) = S(x) -> a = S(x1), b = S(x2), Dup(x1,x2) = x",
+    "Dup(a,b) = Z -> a = Z, b = Z",
+]
+
+
+def ackermann_rules() -> RuleTable:
+    return parse_rules(ACK_SIG, ACK_RULE_TEXTS)
+
+
+def algae_rules() -> RuleTable:
+    return parse_rules(ALGAE_SIG, ALGAE_RULE_TEXTS)
+
+
 # ---------------------------------------------------------------------------
 # nets
 # ---------------------------------------------------------------------------
@@ -286,8 +325,8 @@ class NetBuilder:
     def numeral(self, k: int) -> int:
         """S^k Z as a block: Z first, then each S holds the previous agent."""
         base = self._n
-        lab = np.full(k + 1, S, dtype=np.int32)
-        lab[0] = Z
+        lab = np.full(k + 1, self.sig.label("S"), dtype=np.int32)
+        lab[0] = self.sig.label("Z")
         prt = np.zeros((k + 1, 2), dtype=np.int32)
         prt[1:, 0] = np.arange(base, base + k, dtype=np.int32)
         self._labels.append(lab)
@@ -373,6 +412,25 @@ def fib_net(n: int) -> Net:
     x = nb.numeral(n)
     nb.eq(nb.agent(FIB, r), x)
     return nb.build(family="fib", n=n)
+
+
+def ackermann_net(m: int, n: int) -> Net:
+    """<r | A(S^n Z, r) = S^m Z>: Ackermann(m, n)."""
+    nb = NetBuilder(ACK_SIG)
+    r = nb.name()
+    y = nb.numeral(n)
+    x = nb.numeral(m)
+    nb.eq(nb.agent("A", y, r), x)
+    return nb.build(family="ackermann", m=m, n=n)
+
+
+def algae_net(n: int) -> Net:
+    """<r | GA(r) = S^n Z>: generation n of the algae L-System from axiom A."""
+    nb = NetBuilder(ALGAE_SIG)
+    r = nb.name()
+    x = nb.numeral(n)
+    nb.eq(nb.agent("GA", r), x)
+    return nb.build(family="algae", n=n)
 
 
 def add_tree_net(values: Sequence[int]) -> Net:

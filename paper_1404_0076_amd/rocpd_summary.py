@@ -2,11 +2,17 @@
 
     python -m paper_1404_0076_amd.rocpd_summary trace  DIR   [--kernel NAME] [--last N]
     python -m paper_1404_0076_amd.rocpd_summary counters DIR [--kernel NAME] [--last N]
+    python -m paper_1404_0076_amd.rocpd_summary hbm --fetch DIR --write DIR
+        --copy-fetch DIR --copy-write DIR --copy-bytes N --bench-json FILE --sources-hash H
 
 ``trace``: per-kernel calls / total / average duration from a --kernel-trace
 run, plus the last N dispatches of the selected kernel.  ``counters``: the
 per-dispatch value of every collected counter (summed over its instances) for
-the selected kernel's last N dispatches.
+the selected kernel's last N dispatches.  ``hbm``: HBM bytes per launch of the
+bench's reduce kernel from one FETCH_SIZE run and one WRITE_SIZE run, each
+scaled by what the same counter reads for a plain device copy of known size;
+the output carries the meta lines (kernel source hash, workload key, bytes per
+launch) that bench.py matches before it reports the figure.
 """
 from __future__ import annotations
 
@@ -59,14 +65,76 @@ def counters(path, kernel, last):
     return "\n".join(out)
 
 
+def _counter_rows(path, kernel, counter):
+    rows = []
+    for db in _dbs(path):
+        con = sqlite3.connect(db)
+        rows += con.execute(
+            "select dispatch_id, sum(value), duration from counters_collection "
+            "where kernel_name like ? and counter_name = ? group by dispatch_id order by start",
+            (f"%{kernel}%", counter)).fetchall()
+    if not rows:
+        raise SystemExit(f"no {counter} rows for {kernel!r} under {path}")
+    return rows
+
+
+def hbm(a):
+    import json
+    bench = None
+    with open(a.bench_json) as fh:
+        for line in fh:
+            line = line.strip()
+            if line.startswith("{"):
+                bench = json.loads(line)
+    if bench is None:
+        raise SystemExit(f"no JSON line in {a.bench_json}")
+    roof = bench["roofline"]
+    kernel = roof["kernel"]
+    fetch = _counter_rows(a.fetch, kernel, "FETCH_SIZE")[-1]
+    write = _counter_rows(a.write, kernel, "WRITE_SIZE")[-1]
+    cf = [v for _, v, _ in _counter_rows(a.copy_fetch, "copyBuffer", "FETCH_SIZE")[-3:]]
+    cw = [v for _, v, _ in _counter_rows(a.copy_write, "copyBuffer", "WRITE_SIZE")[-3:]]
+    kib = a.copy_bytes / 1024.0
+    ff, fw = kib / (sum(cf) / len(cf)), kib / (sum(cw) / len(cw))
+    fb, wb = fetch[1] * 1024.0 * ff, write[1] * 1024.0 * fw
+    alg = roof["algorithmic_bytes"]
+    out = [
+        f"# {kernel} -- {bench['config']['workload']}: HBM counters of the last dispatch",
+        f"# kernel_sources_sha256: {a.sources_hash}",
+        f"# workload_key: {roof['workload_key']}",
+        f"# traffic_bytes_per_launch: {fb + wb:.6e}",
+        f"# FETCH_SIZE {fetch[1]:.1f} KiB (dispatch {fetch[0]}, {fetch[2] / 1e3:.3f} us), "
+        f"WRITE_SIZE {write[1]:.1f} KiB (dispatch {write[0]}, {write[2] / 1e3:.3f} us)",
+        f"# copy calibration: {a.copy_bytes} B copied; FETCH_SIZE reads "
+        f"{', '.join(f'{v:.1f}' for v in cf)} KiB (factor {ff:.3f}), WRITE_SIZE reads "
+        f"{', '.join(f'{v:.1f}' for v in cw)} KiB (factor {fw:.3f})",
+        f"# traffic per launch: fetch {fb:.4e} B + write {wb:.4e} B = {fb + wb:.4e} B",
+        f"# algorithmic bytes per launch (bench.py): {alg:.4e} B; traffic / algorithmic = "
+        f"{(fb + wb) / alg:.2f}",
+    ]
+    return "\n".join(out)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["trace", "counters"])
-    ap.add_argument("path")
+    ap.add_argument("mode", choices=["trace", "counters", "hbm"])
+    ap.add_argument("path", nargs="?", default="")
     ap.add_argument("--kernel", default="")
     ap.add_argument("--last", type=int, default=5)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--copy-fetch")
+    ap.add_argument("--copy-write")
+    ap.add_argument("--copy-bytes", type=int, default=1 << 30)
+    ap.add_argument("--bench-json")
+    ap.add_argument("--sources-hash", default="")
     a = ap.parse_args(argv)
-    print(trace(a.path, a.kernel, a.last) if a.mode == "trace" else counters(a.path, a.kernel, a.last))
+    if a.mode == "hbm":
+        print(hbm(a))
+    elif a.mode == "trace":
+        print(trace(a.path, a.kernel, a.last))
+    else:
+        print(counters(a.path, a.kernel, a.last))
 
 
 if __name__ == "__main__":

@@ -122,3 +122,93 @@ def rhs_agent_counts(rule_texts) -> list:
         rhs = t.split("->", 1)[1]
         out.append(len(re.findall(r"\b[A-Z][A-Za-z0-9]*", rhs)))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Benchmark programs of Section 4.1 (rule texts in nets.ACK_RULE_TEXTS and
+# nets.ALGAE_RULE_TEXTS); histograms in rule order.
+
+
+_ACK_ROWS: dict = {}
+
+
+def ack_value(m: int, n: int) -> int:
+    """Ackermann's function by its definition, A(0, n) = n + 1,
+    A(m, 0) = A(m-1, 1), A(m, n) = A(m-1, A(m, n-1)), one row per m memoised."""
+    if m == 0:
+        return n + 1
+    row = _ACK_ROWS.setdefault(m, [])
+    while len(row) <= n:
+        row.append(ack_value(m - 1, 1) if not row else ack_value(m - 1, row[-1]))
+    return row[n]
+
+
+@lru_cache(maxsize=None)
+def ack_per_rule(m: int, n: int) -> tuple:
+    """[A><Z, A><S, A2><Z, A2><S, Dup><S, Dup><Z] to reduce A(m, n):
+    m = 0 fires A><Z once; m > 0 fires A><S, then n = 0 fires A2><Z and
+    continues as A(m-1, 1), while n > 0 fires A2><S, copies S^(m-1) Z
+    (m-1 Dup><S and one Dup><Z), and runs A(m, n-1) and A(m-1, A(m, n-1))."""
+    if m == 0:
+        return (1, 0, 0, 0, 0, 0)
+    if n == 0:
+        rest = ack_per_rule(m - 1, 1)
+        return tuple(x + d for x, d in zip(rest, (0, 1, 1, 0, 0, 0)))
+    inner = ack_per_rule(m, n - 1)
+    outer = ack_per_rule(m - 1, ack_value(m, n - 1))
+    return tuple(x + y + d for x, y, d in zip(inner, outer, (0, 1, 0, 1, m - 1, 1)))
+
+
+def ack_count(m: int, n: int) -> int:
+    return sum(ack_per_rule(m, n))
+
+
+def algae_string(n: int) -> str:
+    """Generation n of A -> AB, B -> A from the axiom A, by string rewriting."""
+    s = "a"
+    for _ in range(n):
+        s = "".join("ab" if c == "a" else "a" for c in s)
+    return s
+
+
+@lru_cache(maxsize=None)
+def _algae(sym: str, k: int) -> tuple:
+    """[GA><Z, GA><S, GB><Z, GB><S, Dup><S, Dup><Z] to expand one symbol for
+    k generations: GA><S copies S^(k-1) Z (k-1 Dup><S, one Dup><Z) and
+    expands A and B for k-1; GB><S expands A for k-1."""
+    if sym == "a":
+        if k == 0:
+            return (1, 0, 0, 0, 0, 0)
+        a, b = _algae("a", k - 1), _algae("b", k - 1)
+        return tuple(x + y + d for x, y, d in zip(a, b, (0, 1, 0, 0, k - 1, 1)))
+    if k == 0:
+        return (0, 0, 1, 0, 0, 0)
+    return tuple(x + d for x, d in zip(_algae("a", k - 1), (0, 0, 0, 1, 0, 0)))
+
+
+def algae_per_rule(n: int) -> tuple:
+    return _algae("a", n)
+
+
+def algae_count(n: int) -> int:
+    return sum(algae_per_rule(n))
+
+
+def decode_letters(nf, cat: int, letters: dict) -> str:
+    """The single interface term of a normal-form stream (no residuals) read
+    as a binary tree of ``cat`` nodes over nullary letter labels."""
+    nf = [int(v) for v in nf]
+    assert nf[0] == 1, "one interface term expected"
+    out = []
+    pos = 1
+    pending = 1
+    while pending:
+        lab = nf[pos]
+        pos += 1
+        pending -= 1
+        if lab == cat:
+            pending += 2
+        else:
+            out.append(letters[lab])
+    assert nf[pos:] == [0], "no residual equations expected"
+    return "".join(out)

@@ -107,6 +107,80 @@ def test_random_expressions(seed, net):
     assert_same(gpu(R, net), oracle_run(R, net), f"expr {seed}")
 
 
+# rule tables other than arithmetic: the chain example of Section 3.6, a rule
+# that wires its two arguments together, and a rule with five link equations
+# (four argument links and an active pair between two new agents)
+CHAIN_SIG = nets.Signature(["A", "B", "C"], [1, 0, 0])
+LOOP_SIG = nets.Signature(["P", "Q"], [1, 1])
+WIDE_SIG = nets.Signature(["P", "Q", "E", "F"], [2, 2, 0, 0])
+WIDE_RULES = ["P(a, b) = Q(c, d) -> a = E, b = F, c = E, d = F, E = F", "E = F ->"]
+
+
+def wide_net(k):
+    # k pairs joined through names: x(i+1) links pair i to pair i+1, so every
+    # pair's F meets the next pair's E after com; 3k - 1 interactions
+    iface = ["x0"] + [f"r{i}, s{i}" for i in range(k)] + [f"x{k}"]
+    eqs = [f"P(x{i}, r{i}) = Q(s{i}, x{i + 1})" for i in range(k)]
+    return nets.parse_net(WIDE_SIG, f"<{', '.join(iface)} | {', '.join(eqs)}>")
+
+
+def chain_net(length, free=False):
+    links = "".join(f"x{i} = x{i + 1}, " for i in range(length - 1))
+    end = "y" if free else "B"
+    iface = "r, y" if free else "r"
+    return nets.parse_net(CHAIN_SIG, f"<{iface} | A(r) = x0, {links}x{length - 1} = {end}>")
+
+
+OTHER_TABLES = [
+    ("chain", CHAIN_SIG, ["A(r) = B -> r = C"],
+     [chain_net(1), chain_net(5), chain_net(40), chain_net(3, free=True)]),
+    ("loop", LOOP_SIG, ["P(a) = Q(b) -> a = b"],
+     [nets.parse_net(LOOP_SIG, "< | P(x) = Q(x)>"), nets.parse_net(LOOP_SIG, "<r, s | P(r) = Q(s)>")]),
+    ("wide", WIDE_SIG, WIDE_RULES, [wide_net(1), wide_net(7), wide_net(300)]),
+]
+
+
+@pytest.mark.parametrize("engine", [1, 2, 3])
+@pytest.mark.parametrize("wg", [64, 1024])
+def test_engines_agree(engine, wg):
+    # every engine (per-lane interpreter, rule-uniform, rules compiled in at
+    # load time) gives the oracle's normal form, count and histogram
+    for net in (nets.mul_net(30, 41), nets.fib_net(12), nets.config1_add_tree(3, 64, 30), MID,
+                nets.parse_net(nets.ARITH_SIG, "<r, q | S(r) = Z, Add(q, y) = Fib(y)>")):
+        say("engine", engine, wg, net.meta.get("family"))
+        assert_same(gpu(R, net, wg=wg, engine=engine), oracle_run(R, net), f"engine {engine}")
+
+
+@pytest.mark.parametrize("engine", [1, 2, 3])
+@pytest.mark.parametrize("name,sig,texts,cases", OTHER_TABLES, ids=[t[0] for t in OTHER_TABLES])
+def test_other_rule_tables(engine, name, sig, texts, cases):
+    rules = nets.parse_rules(sig, texts)
+    for net in cases:
+        ref = oracle_run(rules, net)
+        say("table", name, engine, net.n_agents, ref.interactions)
+        for wg in (64, 256):
+            assert_same(gpu(rules, net, wg=wg, engine=engine), ref, f"{name} engine {engine}")
+    if name == "wide":
+        assert oracle_run(rules, wide_net(7)).interactions == 3 * 7 - 1
+
+
+@pytest.mark.parametrize("engine", [1, 2, 3])
+def test_batch_engines_agree(engine):
+    batch = [n for _, n in small_exprs(12, 12, 5, 200_000)] + \
+            [nets.mul_net(5, 7), nets.fib_net(9), nets.config1_add_tree(2, 16, 12),
+             nets.parse_net(nets.ARITH_SIG, "<r | S(r) = Z>")]
+    refs = [oracle_run(R, net) for net in batch]
+    caps = [net.n_agents + 4 * r.interactions + 1024 for net, r in zip(batch, refs)]
+    say("batch engine", engine)
+    h = P.batch_load(R, batch, agent_caps=caps, name_caps=[4 * c for c in caps])
+    h.set_config(wg_size=64, engine=engine)
+    assert h.get_config()["engine"] == engine
+    rs = h.reduce()
+    for i in range(len(batch)):
+        assert_same((rs[i], h.readback(i), h.per_rule(i)), refs[i], f"net {i}")
+    h.free()
+
+
 @pytest.mark.parametrize("wg", [64, 128, 256, 512, 1024])
 def test_launch_shapes_agree(wg):
     # uniform confluence: the launch geometry changes the schedule only
