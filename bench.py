@@ -124,7 +124,7 @@ def cpu_baseline(R, net_list, seconds):
 
 def bench_serve(args, P, R, nets, torch):
     """Served workload: Poisson arrivals of nets drawn from the batch mix."""
-    from paper_1404_0076_amd.serve import serve
+    from paper_1404_0076_amd.serve import serve, serve_native
     pool = nets.config5_pool(seed=2, n_nets=args.pool)
     log(f"sizing pool of {len(pool)}")
     used_a, used_n, steps, inter = size_batch(P, R, pool, args.wg or 256)
@@ -133,8 +133,9 @@ def bench_serve(args, P, R, nets, torch):
     rng = np.random.Generator(np.random.PCG64(4))
     pick = rng.integers(0, len(pool), len(arrivals))
     log(f"serving {len(arrivals)} requests at {args.rate}/s")
-    rep = serve(R, pool, arrivals, pick, caps=caps, max_slots=8192, workspace_bytes=48 << 30,
-                round_steps=args.round_steps, wg_size=args.wg)
+    run = serve_native if args.serve_loop == "native" else serve
+    rep = run(R, pool, arrivals, pick, caps=caps, max_slots=8192, workspace_bytes=48 << 30,
+              round_steps=args.round_steps, wg_size=args.wg)
     bad = [s for s in rep.served if s.status not in (P.OK, P.STUCK)]
     if bad:
         raise RuntimeError(f"{len(bad)} requests failed")
@@ -147,7 +148,8 @@ def bench_serve(args, P, R, nets, torch):
         "data": "synthetic",
         "config": {"workload": f"served: Poisson arrivals at {args.rate:g} nets/s for {args.duration:g} s "
                                f"from a pool of {len(pool)} nets (batch mix, seed 2)",
-                   "round_steps": args.round_steps, "requests": len(arrivals)},
+                   "round_steps": args.round_steps, "requests": len(arrivals),
+                   "loop": args.serve_loop},
         "latency_ms": {"p50": rep.latency_ms(50), "p99": rep.latency_ms(99), "max": rep.latency_ms(100)},
         "rounds": rep.rounds, "max_resident": rep.max_resident, "wall_s": rep.wall,
     }
@@ -168,6 +170,8 @@ def main():
     ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals")
     ap.add_argument("--pool", type=int, default=8192, help="serve: request pool size")
     ap.add_argument("--round-steps", type=int, default=256, help="serve: step budget per round")
+    ap.add_argument("--serve-loop", default="native", choices=["native", "python"],
+                    help="serve: the library's serving loop or the Python driver")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--n-nets", type=int, default=4096)
     ap.add_argument("--fib-n", type=int, default=27)

@@ -258,6 +258,36 @@ int inet_server_per_rule(inet_server *s, int64_t ticket, uint64_t *counts, int32
 int inet_server_release(inet_server *s, int64_t ticket);
 int inet_server_stats(const inet_server *s, int64_t *free_bytes, int32_t *free_slots,
                       int32_t *running);
+/* The serving loop run natively (no interpreter between rounds).  Requests
+ * come from a pool packed as for inet_batch_load (net j: agents
+ * [agent_off[j], agent_off[j+1]), equations [eq_off[j], eq_off[j+1]),
+ * n_names[j] names, capacities agent_cap[j] / name_cap[j], either array NULL
+ * for the defaults); the pool is validated and uploaded once into the
+ * server's buffer for the duration of the call.  Request i is pool net
+ * pick[i] arriving arrival_s[i] seconds after the call starts (non-decreasing).
+ * Each round admits the requests that have arrived while a slot and device
+ * bytes are free, installs all of them with one copy and one kernel launch on
+ * `stream`, advances every running net by at most round_steps parallel steps
+ * and harvests the nets that finished; requests arriving during a round are
+ * admitted for the next one.  A request that runs out of capacity is admitted
+ * again with 8x its capacities (up to 4096x).  Per request the call writes its
+ * completion time (seconds since the start), status, interaction count and
+ * steps; the normal forms are not read back.  The server must be idle (no
+ * admitted nets).  INET_ELIMIT when time_limit_s passes, INET_ENOMEM when a
+ * request cannot be admitted into an empty server. */
+typedef struct {
+  int64_t rounds;
+  int32_t max_resident;
+  int32_t retries;
+  double wall_s;
+} inet_serve_stats;
+int inet_server_run(inet_server *s, int32_t n_pool, const int32_t *label, const int32_t *port,
+                    const int64_t *agent_off, const int32_t *eq_lhs, const int32_t *eq_rhs,
+                    const int64_t *eq_off, const int32_t *n_names, const int64_t *agent_cap,
+                    const int64_t *name_cap, int64_t n_req, const double *arrival_s,
+                    const int32_t *pick, uint32_t round_steps, double time_limit_s,
+                    hipStream_t stream, double *done_s, int32_t *status, uint64_t *interactions,
+                    uint32_t *steps, inet_serve_stats *stats);
 void inet_server_free(inet_server *s);
 
 #ifdef __cplusplus

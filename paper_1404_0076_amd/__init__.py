@@ -29,7 +29,7 @@ EXPORTS = [
     "inet_graph_launch", "inet_server_create", "inet_server_set_config", "inet_server_net_bytes",
     "inet_server_submit", "inet_server_step", "inet_server_poll", "inet_server_result",
     "inet_server_per_rule", "inet_server_release", "inet_server_stats", "inet_server_free",
-    "inet_jit_build",
+    "inet_jit_build", "inet_server_run",
 ]
 
 
@@ -91,6 +91,8 @@ def library():
             "inet_server_result": [_P, _I64, _P, _P, _I64, _P],
             "inet_server_per_rule": [_P, _I64, _P, _I32],
             "inet_server_release": [_P, _I64], "inet_server_stats": [_P, _P, _P, _P],
+            "inet_server_run": [_P, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _P, _P,
+                                ctypes.c_uint32, ctypes.c_double, _P, _P, _P, _P, _P, _P],
         }
         for name, args in sig.items():
             f = getattr(lib, name)
@@ -361,6 +363,11 @@ def _result(r) -> Result:
                   r.max_frontier, r.loops)
 
 
+class _ServeStats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int64), ("max_resident", ctypes.c_int32),
+                ("retries", ctypes.c_int32), ("wall_s", ctypes.c_double)]
+
+
 class Server:
     """Continuous batching (inet_server_*): admit nets while others run."""
 
@@ -406,6 +413,43 @@ class Server:
         if rc:
             raise InetError(rc, "inet_server_submit")
         return int(t.value)
+
+    def run(self, pool, arrivals, pick, caps=None, round_steps: int = 256,
+            time_limit: float = 600.0, stream=None) -> dict:
+        """The native serving loop (inet_server_run) over ``pool``: request i
+        is ``pool[pick[i]]`` arriving ``arrivals[i]`` seconds after the start.
+        ``caps[j] = (agent_cap, name_cap)`` or None for the defaults.  Returns
+        per-request completion times, statuses, interaction counts and steps
+        plus the loop's statistics."""
+        from .nets import pack
+        s, _ = _stream_handle(stream)
+        label, port, a_off, eql, eqr, e_off, n_names = pack(pool)
+        label, port = _arr(label, np.int32), _arr(port, np.int32)
+        eql, eqr = _arr(eql, np.int32), _arr(eqr, np.int32)
+        a_off, e_off, n_names = _arr(a_off, np.int64), _arr(e_off, np.int64), _arr(n_names, np.int32)
+        ac = nc = None
+        if caps is not None:
+            ac = _arr(np.asarray([c[0] for c in caps]), np.int64)
+            nc = _arr(np.asarray([c[1] for c in caps]), np.int64)
+        arr = _arr(np.asarray(arrivals, dtype=np.float64), np.float64)
+        pk_ = _arr(np.asarray(pick), np.int32)
+        n = len(arr)
+        done = np.zeros(n, np.float64)
+        status = np.zeros(n, np.int32)
+        inter = np.zeros(n, np.uint64)
+        steps = np.zeros(n, np.uint32)
+        st = _ServeStats()
+        ptr = lambda a: None if a is None else a.ctypes.data  # noqa: E731
+        rc = library().inet_server_run(
+            self._h, len(pool), ptr(label), ptr(port), ptr(a_off), ptr(eql), ptr(eqr), ptr(e_off),
+            ptr(n_names), ptr(ac), ptr(nc), n, ptr(arr), ptr(pk_), round_steps, time_limit, s,
+            done.ctypes.data, status.ctypes.data, inter.ctypes.data, steps.ctypes.data,
+            ctypes.byref(st))
+        if rc:
+            raise InetError(rc, "inet_server_run")
+        return {"done": done, "status": status, "interactions": inter, "steps": steps,
+                "rounds": int(st.rounds), "max_resident": int(st.max_resident),
+                "retries": int(st.retries), "wall": float(st.wall_s)}
 
     def step(self, max_steps: int, stream=None):
         s, _ = _stream_handle(stream)

@@ -411,145 +411,358 @@ __device__ __forceinline__ void pass_uniform(INET_PASS_ARGS) {
 #ifdef INET_STATIC_RULES
 // ---------------------------------------------------------------------------
 // Engine 3: the rule table is compile-time data (namespace rt, generated at
-// load time).  Each rule's right-hand side is straight-line code: operand
-// choices, agent counts, arities and link counts are all constants.
+// load time).  Each rule's right-hand side is straight-line code: labels,
+// arities, operand kinds and link counts are constants.  A pass walks the
+// distinct rules among the wave's lanes twice: the first walk allocates,
+// writes the new agents and issues every name-cell exchange of the wave; the
+// second decides each link knowing the rule's operand kinds (by then the
+// exchanges of all groups are in flight together).  A single-wave engine
+// keeps its heap tops, frontier count and error flag in registers.
+
+template <int V>
+struct IC {
+  static constexpr int value = V;
+};
+
+// the rule code of every rule present among the wave's lanes, in rule order:
+// straight-line code (one ballot per rule), so values produced for one rule
+// (exchange results in flight) are not copied around a loop, which would wait
+// for them
+template <int R, class F>
+__device__ __forceinline__ void for_rules(int rid, F &&f) {
+  if constexpr (R < rt::NR) {
+    const unsigned long long gm = ballot(rid == R);
+    if (gm) f(IC<R>{}, gm);
+    for_rules<R + 1>(rid, f);
+  }
+}
+
+struct Lane {  // a lane's active pair as the rule is stored, and its allocations
+  int a, b, pa0, pa1, pb0, pb1, my_a, my_n;
+};
 
 template <int OP>
-__device__ __forceinline__ int opnd(int a, int b, int pa0, int pa1, int pb0, int pb1, int my_a,
-                                    int my_n) {
+__device__ __forceinline__ int opnd(const Lane &L) {
   constexpr int kind = OP >> 4, idx = OP & 15;
   if constexpr (kind == OP_AUX) {
-    if constexpr (idx == 0) return pa0;
-    else if constexpr (idx == 1) return pa1;
-    else if constexpr (idx == 2) return pb0;
-    else return pb1;
+    if constexpr (idx == 0) return L.pa0;
+    else if constexpr (idx == 1) return L.pa1;
+    else if constexpr (idx == 2) return L.pb0;
+    else return L.pb1;
   } else if constexpr (kind == OP_NEW) {
-    if constexpr (idx == 0) return a;
-    else if constexpr (idx == 1) return b;
-    else return my_a + (idx - 2);
+    if constexpr (idx == 0) return L.a;
+    else if constexpr (idx == 1) return L.b;
+    else return L.my_a + (idx - 2);
   } else {
-    return -1 - (my_n + idx);
+    return -1 - (L.my_n + idx);
   }
 }
 
-#define INET_OPND(op) opnd<(op)>(a, b, pa0, pa1, pb0, pb1, my_a, my_n)
+// an opaque copy: address arithmetic and tests on the value then stay inside
+// the rule code that uses them (otherwise they are hoisted out of the walk,
+// for every operand of every rule, and their masks spill)
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+__device__ __forceinline__ Lane opaque(const Lane &L) {
+  Lane o;
+  o.a = opaque(L.a);
+  o.b = opaque(L.b);
+  o.pa0 = opaque(L.pa0);
+  o.pa1 = opaque(L.pa1);
+  o.pb0 = opaque(L.pb0);
+  o.pb1 = opaque(L.pb1);
+  o.my_a = opaque(L.my_a);
+  o.my_n = opaque(L.my_n);
+  return o;
+}
+
+// the engine's counters: LDS words shared by the waves of the workgroup, or
+// wave-uniform registers when the engine is one wave
+template <bool SOLO>
+struct Ctr;
+
+template <>
+struct Ctr<true> {
+  int agent_top, name_top, next, nstuck, err;
+  __device__ __forceinline__ int agents(int n, int, int) {
+    const int b = agent_top;
+    agent_top += n;
+    return b;
+  }
+  __device__ __forceinline__ int names(int n, int, int) {
+    const int b = name_top;
+    name_top += n;
+    return b;
+  }
+  __device__ __forceinline__ int append(int n) {
+    const int b = next;
+    next += n;
+    return b;
+  }
+  __device__ __forceinline__ int stuck(int n) {
+    const int b = nstuck;
+    nstuck += n;
+    return b;
+  }
+  __device__ __forceinline__ void fail_uniform(int, int) { err = ST_ENOMEM; }
+  // wave-uniform call: a lane out of queue space, or a broken chain invariant
+  __device__ __forceinline__ void fail(bool nomem, bool internal) {
+    if (ballot(internal)) err = ST_EINTERNAL;
+    else if (ballot(nomem)) err = ST_ENOMEM;
+  }
+};
+
+template <>
+struct Ctr<false> {
+  int *agent_top, *name_top, *next, *nstuck, *status;
+  __device__ __forceinline__ int take(int *p, int n, int lane, int lead) {
+    int b = 0;
+    if (lane == lead) b = atomicAdd(p, n);
+    return __builtin_amdgcn_readlane(b, lead);
+  }
+  __device__ __forceinline__ int agents(int n, int lane, int lead) { return take(agent_top, n, lane, lead); }
+  __device__ __forceinline__ int names(int n, int lane, int lead) { return take(name_top, n, lane, lead); }
+  __device__ __forceinline__ int append(int n) { return take(next, n, __lane_id(), 0); }
+  __device__ __forceinline__ int stuck(int n) { return take(nstuck, n, __lane_id(), 0); }
+  __device__ __forceinline__ void fail_uniform(int lane, int lead) {
+    if (lane == lead) *status = ST_ENOMEM;
+  }
+  __device__ __forceinline__ void fail(bool nomem, bool internal) {
+    if (internal) *status = ST_EINTERNAL;
+    else if (nomem) *status = ST_ENOMEM;
+  }
+};
 
 template <int R, int K>
-__device__ __forceinline__ void st_agents(int a, int b, int pa0, int pa1, int pb0, int pb1,
-                                          int my_a, int my_n, gint *label, gint *port0,
-                                          gint *port1) {
+__device__ __forceinline__ void st_agents(const Lane &L, gint *label, gint *port0, gint *port1) {
   if constexpr (K < rt::T[R][RT_NNEW]) {
-    constexpr int L = rt::T[R][RT_LABEL + K];
-    const unsigned slot = K == 0 ? (unsigned)a : (K == 1 ? (unsigned)b : (unsigned)(my_a + K - 2));
-    *at(label, slot) = L;
-    if constexpr (rt::ARITY[L] > 0) *at(port0, slot) = INET_OPND(rt::T[R][RT_PORT + 2 * K]);
-    if constexpr (rt::ARITY[L] > 1) *at(port1, slot) = INET_OPND(rt::T[R][RT_PORT + 2 * K + 1]);
-    st_agents<R, K + 1>(a, b, pa0, pa1, pb0, pb1, my_a, my_n, label, port0, port1);
+    constexpr int LB = rt::T[R][RT_LABEL + K];
+    const unsigned slot =
+        K == 0 ? (unsigned)L.a : (K == 1 ? (unsigned)L.b : (unsigned)(L.my_a + K - 2));
+    *at(label, slot) = LB;
+    if constexpr (rt::ARITY[LB] > 0) *at(port0, slot) = opnd<rt::T[R][RT_PORT + 2 * K]>(L);
+    if constexpr (rt::ARITY[LB] > 1) *at(port1, slot) = opnd<rt::T[R][RT_PORT + 2 * K + 1]>(L);
+    st_agents<R, K + 1>(L, label, port0, port1);
   }
 }
 
-template <int R, int J, int MAXL>
-__device__ __forceinline__ void st_links(int a, int b, int pa0, int pa1, int pb0, int pb1,
-                                         int my_a, int my_n, gint *bind, int (&eu)[MAXL],
-                                         int (&ev)[MAXL], int (&eo)[MAXL]) {
-  if constexpr (J < rt::T[R][RT_NEQ] && J < MAXL) {
-    constexpr int OU = rt::T[R][RT_EQ + 2 * J], OV = rt::T[R][RT_EQ + 2 * J + 1];
-    int u = INET_OPND(OU);
-    int v = INET_OPND(OV);
-    if constexpr ((OU >> 4) == OP_NEW) {  // u is an agent: the name side, if any, is v
-      const int t = u; u = v; v = t;
-    } else if constexpr ((OU >> 4) == OP_AUX) {
+// link J of rule R as (u, v) with the name side, if there is one, in u
+template <int R, int J>
+__device__ __forceinline__ void link_sides(const Lane &L, int &u, int &v) {
+  constexpr int OU = rt::T[R][RT_EQ + 2 * J], OV = rt::T[R][RT_EQ + 2 * J + 1];
+  if constexpr ((OU >> 4) == OP_NEW) {
+    u = opnd<OV>(L);
+    v = opnd<OU>(L);
+  } else {
+    u = opnd<OU>(L);
+    v = opnd<OV>(L);
+    if constexpr ((OU >> 4) == OP_AUX) {  // an argument: agent or name at run time
       if (u >= 0) { const int t = u; u = v; v = t; }
     }
-    eu[J] = u;
-    ev[J] = v;
-    if (u < 0 && u != v) eo[J] = xchg(at(bind, (unsigned)~u), v);
-    st_links<R, J + 1, MAXL>(a, b, pa0, pa1, pb0, pb1, my_a, my_n, bind, eu, ev, eo);
   }
 }
 
-template <int R, int MAXL>
-__device__ __forceinline__ void apply_rule(unsigned long long gm, int lead, int lane, int a, int b,
-                                           int pa0, int pa1, int pb0, int pb1, const NetDesc &D,
-                                           gint *label, gint *port0, gint *port1, gint *bind,
-                                           int *s_agent_top, int *s_name_top,
-                                           unsigned long long *s_rc, int *s_status,
-                                           int (&eu)[MAXL], int (&ev)[MAXL], int (&eo)[MAXL],
-                                           int &lneq, bool mine) {
-  constexpr int nalloc = rt::T[R][RT_NALLOC], nfresh = rt::T[R][RT_NFRESH];
-  const int cnt = __popcll(gm);
-  const int rank = count_below(gm);
-  int ba = 0, bn = 0;
-  if (lane == lead) {
-    if constexpr (nalloc > 0) ba = atomicAdd(s_agent_top, nalloc * cnt);
-    if constexpr (nfresh > 0) bn = atomicAdd(s_name_top, nfresh * cnt);
-    atomicAdd(&s_rc[R], (unsigned long long)cnt);
+template <int R, int J>
+struct LinkKind {
+  static constexpr int OU = rt::T[R][RT_EQ + 2 * J], OV = rt::T[R][RT_EQ + 2 * J + 1];
+  static constexpr bool both_new = (OU >> 4) == OP_NEW && (OV >> 4) == OP_NEW;
+  // after link_sides, a v that survives the "both agents" test is an agent
+  static constexpr bool v_agent = (OU >> 4) == OP_NEW || (OV >> 4) == OP_NEW;
+};
+
+// first walk, links: issue the exchange of every link whose name side is a name
+template <int R, int J, int MAXL>
+__device__ __forceinline__ void issue_links(const Lane &L, gint *bind, int (&eo)[MAXL]) {
+  if constexpr (J < rt::T[R][RT_NEQ] && J < MAXL) {
+    if constexpr (!LinkKind<R, J>::both_new) {
+      int u, v;
+      link_sides<R, J>(L, u, v);
+      int e = EMPTY;
+      if (u < 0 && u != v) e = xchg(at(bind, (unsigned)~u), v);
+      eo[J] = e;
+    }
+    issue_links<R, J + 1, MAXL>(L, bind, eo);
   }
-  if constexpr (nalloc > 0) ba = __builtin_amdgcn_readlane(ba, lead);
-  if constexpr (nfresh > 0) bn = __builtin_amdgcn_readlane(bn, lead);
-  const int my_a = ba + nalloc * rank, my_n = bn + nfresh * rank;
-  bool ok = mine;
-  if constexpr (nalloc > 0 || nfresh > 0) {
-    if (mine && (my_a + nalloc > D.agent_cap || my_n + nfresh > D.name_cap)) {
-      *s_status = ST_ENOMEM;
-      ok = false;
+}
+
+// second walk, links: a new active pair (pu[J] >= 0: both sides are agents),
+// a parked side, a closed loop, or a chain (the exchange met a parked name:
+// com carries on along it)
+template <int R, int J, int MAXL>
+__device__ __forceinline__ void decide_links(const Lane &L, gint *bind, const int (&eo)[MAXL],
+                                             int (&pu)[MAXL], int (&pv)[MAXL], int &loops,
+                                             bool &bad) {
+  if constexpr (J < rt::T[R][RT_NEQ] && J < MAXL) {
+    using K = LinkKind<R, J>;
+    if constexpr (K::both_new) {
+      pu[J] = opnd<K::OV>(L);
+      pv[J] = opnd<K::OU>(L);
+    } else {
+      int u, v;
+      link_sides<R, J>(L, u, v);
+      const int o = opaque(eo[J]);
+      bool chain = false;
+      if (u >= 0) {
+        pu[J] = u;
+        pv[J] = v;
+      } else if (u == v) {
+        loops++;
+      } else if (o != EMPTY) {
+        if (o >= 0 && (K::v_agent || v >= 0)) {
+          pu[J] = o;
+          pv[J] = v;
+        } else {
+          chain = true;
+        }
+      }
+      if (ballot(chain)) {
+        if (chain) {
+          int ou = -1, ov = 0;
+          int guard = 0;
+          if (!link(o, v, bind, ou, ov, loops, &guard)) ou = -1;
+          if (guard) bad = true;
+          pu[J] = ou;
+          pv[J] = ov;
+        }
+      }
+    }
+    decide_links<R, J + 1, MAXL>(L, bind, eo, pu, pv, loops, bad);
+  }
+}
+
+template <int QCAP, int MAXL, bool SOLO>
+__device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, int lb, int pa0,
+                                            int pa1, int pb0, int pb1, const NetDesc &D,
+                                            gint *label, gint *port0, gint *port1, gint *bind,
+                                            gint2 *stuck, const int *rule_of, Pair *nq_l,
+                                            gint2 *nq_g, Ctr<SOLO> &C, int *s_loops,
+                                            unsigned long long *s_rc) {
+  const int lane = __lane_id();
+  const int code = rule_of[valid ? la * rt::NS + lb : 0];
+  // take the loaded ports through a copy on every path: later rule blocks then
+  // never wait on these loads, a wait that would also hold for the exchanges
+  // issued by earlier blocks
+  pa0 = opaque(pa0);
+  pa1 = opaque(pa1);
+  pb0 = opaque(pb0);
+  pb1 = opaque(pb1);
+  bool lane_err = false;
+  const bool stk = valid && code < 0;
+  const unsigned long long sm = ballot(stk);
+  if (sm) {  // active pairs without a rule: residuals
+    const int sb = C.stuck(__popcll(sm));
+    if (stk) {
+      const int si = sb + count_below(sm);
+      if (si < D.scap) *at2(stuck, (unsigned)si) = pk(a, b);
+      else lane_err = true;
     }
   }
-  if (ok) {
-    st_agents<R, 0>(a, b, pa0, pa1, pb0, pb1, my_a, my_n, label, port0, port1);
-#pragma unroll
-    for (int f = 0; f < nfresh; f++) *at(bind, (unsigned)(my_n + f)) = EMPTY;
-    lneq = rt::T[R][RT_NEQ];
-    st_links<R, 0, MAXL>(a, b, pa0, pa1, pb0, pb1, my_a, my_n, bind, eu, ev, eo);
-  }
-}
-
-template <int R, int MAXL>
-__device__ __forceinline__ void dispatch_rule(int r, unsigned long long gm, int lead, int lane,
-                                              int a, int b, int pa0, int pa1, int pb0, int pb1,
-                                              const NetDesc &D, gint *label, gint *port0,
-                                              gint *port1, gint *bind, int *s_agent_top,
-                                              int *s_name_top, unsigned long long *s_rc,
-                                              int *s_status, int (&eu)[MAXL], int (&ev)[MAXL],
-                                              int (&eo)[MAXL], int &lneq, bool mine) {
-  if constexpr (R < rt::NR) {
-    if (r == R)
-      apply_rule<R, MAXL>(gm, lead, lane, a, b, pa0, pa1, pb0, pb1, D, label, port0, port1, bind,
-                          s_agent_top, s_name_top, s_rc, s_status, eu, ev, eo, lneq, mine);
-    else
-      dispatch_rule<R + 1, MAXL>(r, gm, lead, lane, a, b, pa0, pa1, pb0, pb1, D, label, port0,
-                                 port1, bind, s_agent_top, s_name_top, s_rc, s_status, eu, ev, eo,
-                                 lneq, mine);
-  }
-}
-
-template <int QCAP, int MAXL>
-__device__ __forceinline__ void pass_static(INET_PASS_ARGS) {
-  const int code = valid ? rule_of[valid ? la * ns + lb : 0] : -1;
-  if (ballot(valid && code < 0)) stuck_push<QCAP>(valid && code < 0, a, b, D, stuck, s_nstuck, s_status);
   const bool act = valid && code >= 0;
   const int rid = act ? (code >> 1) : -1;
+  Lane L;
+  L.a = a; L.b = b; L.pa0 = pa0; L.pa1 = pa1; L.pb0 = pb0; L.pb1 = pb1;
+  L.my_a = 0; L.my_n = 0;
   if (act && (code & 1)) {
-    int t = a; a = b; b = t;
-    t = pa0; pa0 = pb0; pb0 = t;
-    t = pa1; pa1 = pb1; pb1 = t;
+    L.a = b; L.b = a;
+    L.pa0 = pb0; L.pb0 = pa0;
+    L.pa1 = pb1; L.pb1 = pa1;
   }
-  int lneq = 0;
-  int eu[MAXL], ev[MAXL], eo[MAXL];
+  // exchange results, one register per (rule, link): exchanges of different
+  // rules are then in flight together without write-after-write waits
+  int eo[rt::NR > 0 ? rt::NR : 1][MAXL];
+  int pu[MAXL], pv[MAXL];  // new active pair of link j, pu[j] < 0 if none
 #pragma unroll
-  for (int j = 0; j < MAXL; j++) { eu[j] = 0; ev[j] = 0; eo[j] = EMPTY; }
-  unsigned long long rem = ballot(act);
-  const int lane = __lane_id();
-  while (rem) {
-    const int lead = __builtin_ctzll(rem);
-    const int r = __builtin_amdgcn_readlane(rid, lead);
-    const bool mine = rid == r;
-    const unsigned long long gm = ballot(mine);
-    rem &= ~gm;
-    dispatch_rule<0, MAXL>(r, gm, lead, lane, a, b, pa0, pa1, pb0, pb1, D, label, port0, port1,
-                           bind, s_agent_top, s_name_top, s_rc, s_status, eu, ev, eo, lneq, mine);
+  for (int j = 0; j < MAXL; j++) { pu[j] = -1; pv[j] = 0; }
+  // first walk: allocate, write the new agents, issue the exchanges
+  for_rules<0>(rid, [&](auto ic, unsigned long long gm) {
+      constexpr int R = decltype(ic)::value;
+      constexpr int nalloc = rt::T[R][RT_NALLOC], nfresh = rt::T[R][RT_NFRESH];
+      const int lead = __builtin_ctzll(gm);
+      const bool mine = rid == R;
+      const int cnt = __popcll(gm);
+      int ba = 0, bn = 0;
+      if constexpr (nalloc > 0) ba = C.agents(nalloc * cnt, lane, lead);
+      if constexpr (nfresh > 0) bn = C.names(nfresh * cnt, lane, lead);
+      if (lane == lead) atomicAdd(&s_rc[R], (unsigned long long)cnt);
+      if ((nalloc > 0 && ba + nalloc * cnt > D.agent_cap) ||
+          (nfresh > 0 && bn + nfresh * cnt > D.name_cap)) {
+        C.fail_uniform(lane, lead);
+        return;
+      }
+      if (mine) {
+        const int rank = count_below(gm);
+        Lane X = opaque(L);
+        X.my_a = ba + nalloc * rank;
+        X.my_n = bn + nfresh * rank;
+        L.my_a = X.my_a;
+        L.my_n = X.my_n;
+        st_agents<R, 0>(X, label, port0, port1);
+#pragma unroll
+        for (int f = 0; f < nfresh; f++) *at(bind, (unsigned)(X.my_n + f)) = EMPTY;
+        issue_links<R, 0, MAXL>(X, bind, eo[R]);
+      }
+  });
+  // second walk: decide every link
+  int loops = 0;
+  bool bad = false;
+  for_rules<0>(rid, [&](auto ic, unsigned long long) {
+    constexpr int R = decltype(ic)::value;
+    if (rid == R) decide_links<R, 0, MAXL>(opaque(L), bind, eo[R], pu, pv, loops, bad);
+  });
+  // append the wave's new active pairs
+  unsigned long long m[MAXL];
+  int tot = 0;
+#pragma unroll
+  for (int j = 0; j < MAXL; j++) {
+    m[j] = ballot(pu[j] >= 0);
+    tot += __popcll(m[j]);
   }
-  finish_links<QCAP, MAXL>(lneq, eu, ev, eo, D, bind, nq_l, nq_g, ncnt, s_status, s_loops);
+  if (tot) {
+    int base = C.append(tot);
+#pragma unroll
+    for (int j = 0; j < MAXL; j++) {
+      if (pu[j] >= 0) {
+        const int i = base + count_below(m[j]);
+        if (i < QCAP) nq_l[i] = mkpair(pu[j], pv[j]);
+        else if (i < D.qcap) *at2(nq_g, (unsigned)i) = pk(pu[j], pv[j]);
+        else lane_err = true;
+      }
+      base += __popcll(m[j]);
+    }
+  }
+  if (loops) atomicAdd(s_loops, loops);
+  C.fail(lane_err, bad);
+}
+
+// the active pair of frontier slot base + tid and its two agents; lanes
+// without a pair read slot 0 (always allocated) and stay idle, so the loads
+// need no branch
+template <int WG, int QCAP>
+__device__ __forceinline__ void fetch_pair(int base, int n, int tid, const Pair *cq_l,
+                                           const gint2 *cq_g, gint *label, gint *port0,
+                                           gint *port1, bool &valid, int &a, int &b, int &la,
+                                           int &lb, int &pa0, int &pa1, int &pb0, int &pb1) {
+  const int i = base + tid;
+  valid = i < n;
+  Pair rx = mkpair(0, 0);
+  if (base + WG <= QCAP) {
+    rx = cq_l[valid ? i : 0];
+  } else if (valid) {
+    if (i < QCAP) rx = cq_l[i];
+    else rx = unpk(*at2((gint2 *)cq_g, (unsigned)i));
+  }
+  if (!valid) rx = mkpair(0, 0);
+  a = rx.x;
+  b = rx.y;
+  la = *at(label, (unsigned)a);
+  lb = *at(label, (unsigned)b);
+  pa0 = *at(port0, (unsigned)a);
+  pa1 = *at(port1, (unsigned)a);
+  pb0 = *at(port0, (unsigned)b);
+  pb1 = *at(port1, (unsigned)b);
 }
 #endif  // INET_STATIC_RULES
 
@@ -578,7 +791,7 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
     __syncthreads();
     if (tid == 0) s_net = atomicAdd(counter, 1);
     __syncthreads();
-    const int k = s_net;
+    const int k = __builtin_amdgcn_readfirstlane(s_net);
     if (k >= n_nets) break;
     const NetDesc D = descs[order[k]];
     NetState *st = D.st;
@@ -630,6 +843,92 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
       for (int i = tid; i < nl; i += WG) q[cur][i] = unpk(g[i]);
     }
 
+#ifdef INET_STATIC_RULES
+    if constexpr (ENGINE == 3) {
+      constexpr bool SOLO = WG == 64;
+      if constexpr (SOLO) {
+        // one wave: the counters live in registers; the wave's own memory
+        // operations are performed in order, so no barrier separates steps
+        __syncthreads();
+        Ctr<true> C;
+        C.agent_top = __builtin_amdgcn_readfirstlane(s_agent_top);
+        C.name_top = __builtin_amdgcn_readfirstlane(s_name_top);
+        C.nstuck = __builtin_amdgcn_readfirstlane(s_nstuck);
+        C.err = __builtin_amdgcn_readfirstlane(s_status);
+        C.next = 0;
+        int n = __builtin_amdgcn_readfirstlane(s_cnt[ci]);
+        int maxf = __builtin_amdgcn_readfirstlane(s_maxf);
+        while (n > 0 && C.err >= 0 && steps < stop) {
+          if (n > maxf) maxf = n;
+          const Pair *cq_l = q[cur];
+          const gint2 *cq_g = cur ? queue1 : queue0;
+          Pair *nq_l = q[cur ^ 1];
+          gint2 *nq_g = cur ? queue0 : queue1;
+          C.next = 0;
+          for (int base = 0; base < n; base += WG) {
+            bool valid;
+            int a, b, la, lb, pa0, pa1, pb0, pb1;
+            fetch_pair<WG, QCAP>(base, n, tid, cq_l, cq_g, label, port0, port1, valid, a, b, la,
+                                 lb, pa0, pa1, pb0, pb1);
+            pass_static<QCAP, MAXL, true>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, label, port0,
+                                          port1, bind, stuck, rule_of, nq_l, nq_g, C, &s_loops,
+                                          s_rc);
+          }
+          // lanes of one wave need no cache action or wait to see each
+          // other's writes (wavefront scope); the fence only keeps the
+          // compiler from moving memory operations across steps
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          steps++;
+          cur ^= 1;
+          n = C.next;
+        }
+        __syncthreads();
+        if (tid == 0) {
+          s_cnt[ci] = n;
+          s_agent_top = C.agent_top;
+          s_name_top = C.name_top;
+          s_nstuck = C.nstuck;
+          s_maxf = maxf;
+          if (C.err < 0) s_status = C.err;
+        }
+        __syncthreads();
+      } else {
+        Ctr<false> C;
+        C.agent_top = &s_agent_top;
+        C.name_top = &s_name_top;
+        C.nstuck = &s_nstuck;
+        C.status = &s_status;
+        for (;;) {
+          __syncthreads();
+          const int n = s_cnt[ci];
+          if (n == 0 || s_status < 0 || steps >= stop) break;
+          const int cn = ci == 2 ? 0 : ci + 1;
+          const int cnn = cn == 2 ? 0 : cn + 1;
+          if (tid == 0) {
+            s_cnt[cnn] = 0;
+            if (n > s_maxf) s_maxf = n;
+          }
+          const Pair *cq_l = q[cur];
+          const gint2 *cq_g = cur ? queue1 : queue0;
+          Pair *nq_l = q[cur ^ 1];
+          gint2 *nq_g = cur ? queue0 : queue1;
+          C.next = &s_cnt[cn];
+          for (int base = 0; base < n; base += WG) {
+            bool valid;
+            int a, b, la, lb, pa0, pa1, pb0, pb1;
+            fetch_pair<WG, QCAP>(base, n, tid, cq_l, cq_g, label, port0, port1, valid, a, b, la,
+                                 lb, pa0, pa1, pb0, pb1);
+            pass_static<QCAP, MAXL, false>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, label,
+                                           port0, port1, bind, stuck, rule_of, nq_l, nq_g, C,
+                                           &s_loops, s_rc);
+          }
+          steps++;
+          cur ^= 1;
+          ci = cn;
+        }
+      }
+    } else
+#endif
     for (;;) {
       __syncthreads();
       const int n = s_cnt[ci];
@@ -662,14 +961,7 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
         const int la = *at(label, ua), lb = *at(label, ub);
         const int pa0 = *at(port0, ua), pa1 = *at(port1, ua);
         const int pb0 = *at(port0, ub), pb1 = *at(port1, ub);
-        if constexpr (ENGINE == 3) {
-#ifdef INET_STATIC_RULES
-          pass_static<QCAP, MAXL>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, label, port0, port1,
-                                  bind, stuck, rule_of, templ, arity, g_templ, g_arity, ns, nq_l,
-                                  nq_g, &s_cnt[cn], &s_status, &s_agent_top, &s_name_top,
-                                  &s_nstuck, &s_loops, s_rc);
-#endif
-        } else if constexpr (ENGINE == 1)
+        if constexpr (ENGINE == 1)
           pass_interp<QCAP>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, label, port0, port1, bind,
                             stuck, rule_of, templ, arity, g_templ, g_arity, ns, nq_l, nq_g,
                             &s_cnt[cn], &s_status, &s_agent_top, &s_name_top, &s_nstuck, &s_loops,
@@ -745,28 +1037,46 @@ __global__ __launch_bounds__(256) void k_jump_grid(const NetDesc *__restrict__ d
   jump_cells((gint *)D.bind, blockIdx.x * 256 + threadIdx.x, nn, gridDim.x * 256);
 }
 
+// restore one net to its loaded state with the lanes tid, tid + stride, ...
+__device__ __forceinline__ void reset_net(const NetDesc &D, int nr, int tid, int stride) {
+  for (int i = tid; i < D.n_agents0; i += stride) {
+    D.label[i] = D.init_label[i];
+    D.port0[i] = D.init_port[2 * i];
+    D.port1[i] = D.init_port[2 * i + 1];
+  }
+  gint2 *q0 = (gint2 *)D.queue0;
+  for (int i = tid; i < D.n_eqs0; i += stride) q0[i] = pk(D.init_eq[2 * i], D.init_eq[2 * i + 1]);
+  for (int i = tid; i < D.n_names0; i += stride) D.bind[i] = EMPTY;
+  for (int i = tid; i < nr; i += stride) D.per_rule[i] = 0ull;
+  if (tid == 0) {
+    NetState s = {};
+    s.agent_top = D.n_agents0;
+    s.name_top = D.n_names0;
+    s.frontier = D.n_eqs0;
+    s.phase = PHASE_INIT;
+    *D.st = s;
+  }
+}
+
 // restore nets to their loaded state: all n nets, or the n listed in idx
 __global__ __launch_bounds__(256) void k_reset(const NetDesc *__restrict__ descs,
                                                const int *__restrict__ idx, int n, int nr) {
+  for (int k = blockIdx.x; k < n; k += gridDim.x) reset_net(descs[idx ? idx[k] : k], nr, threadIdx.x, 256);
+}
+
+// install admitted nets: each record's descriptor goes to its slot and the net
+// is reset from its (already resident) initial image
+__global__ __launch_bounds__(256) void k_admit(const AdmitRec *__restrict__ recs, int n,
+                                               NetDesc *__restrict__ descs, int nr) {
+  __shared__ NetDesc sd;
   for (int k = blockIdx.x; k < n; k += gridDim.x) {
-    const NetDesc D = descs[idx ? idx[k] : k];
-    for (int i = threadIdx.x; i < D.n_agents0; i += 256) {
-      D.label[i] = D.init_label[i];
-      D.port0[i] = D.init_port[2 * i];
-      D.port1[i] = D.init_port[2 * i + 1];
-    }
-    gint2 *q0 = (gint2 *)D.queue0;
-    for (int i = threadIdx.x; i < D.n_eqs0; i += 256) q0[i] = pk(D.init_eq[2 * i], D.init_eq[2 * i + 1]);
-    for (int i = threadIdx.x; i < D.n_names0; i += 256) D.bind[i] = EMPTY;
-    for (int i = threadIdx.x; i < nr; i += 256) D.per_rule[i] = 0ull;
+    __syncthreads();
     if (threadIdx.x == 0) {
-      NetState s = {};
-      s.agent_top = D.n_agents0;
-      s.name_top = D.n_names0;
-      s.frontier = D.n_eqs0;
-      s.phase = PHASE_INIT;
-      *D.st = s;
+      sd = recs[k].desc;
+      descs[recs[k].slot] = recs[k].desc;
     }
+    __syncthreads();
+    reset_net(sd, nr, threadIdx.x, 256);
   }
 }
 

@@ -93,6 +93,13 @@ struct NetDesc {
   int32_t order;  // position in the launch order (largest nets first)
 };
 
+// a net admitted by the serving loop: its descriptor and the slot it takes
+struct AdmitRec {
+  NetDesc desc;
+  int32_t slot;
+  int32_t pad;
+};
+
 // status codes as seen by the kernels (mirror inet_status)
 enum { ST_OK = 0, ST_STUCK = 1, ST_ENOMEM = -2, ST_ELIMIT = -3, ST_EINTERNAL = -8 };
 

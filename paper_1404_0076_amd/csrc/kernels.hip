@@ -98,6 +98,13 @@ int launch_reset(const NetDesc *d, const int32_t *idx, int n, int nr, hipStream_
   return hipGetLastError() == hipSuccess ? INET_OK : INET_EHIP;
 }
 
+int launch_admit(const AdmitRec *d_recs, int n, NetDesc *d_descs, int nr, hipStream_t s) {
+  const int grid = n < 4096 ? n : 4096;
+  if (grid <= 0) return INET_OK;
+  hipLaunchKernelGGL(k_admit, dim3(grid), dim3(256), 0, s, d_recs, n, d_descs, nr);
+  return hipGetLastError() == hipSuccess ? INET_OK : INET_EHIP;
+}
+
 int launch_zero(int32_t *p, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, p, n);
   return hipGetLastError() == hipSuccess ? INET_OK : INET_EHIP;

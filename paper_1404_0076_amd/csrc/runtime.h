@@ -34,6 +34,7 @@ struct LaunchShape {
   int maxl;    // largest number of link equations of any rule
 };
 int launch_reset(const NetDesc *d_descs, const int32_t *d_idx, int n, int nr, hipStream_t s);
+int launch_admit(const AdmitRec *d_recs, int n, NetDesc *d_descs, int nr, hipStream_t s);
 int launch_zero(int32_t *p, int n, hipStream_t s);
 int launch_reduce(const CompiledRules &R, const LaunchShape &shape, int grid,
                   const NetDesc *d_descs, const int32_t *d_order, int n_nets, int32_t *d_counter,

@@ -11,8 +11,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstring>
+#include <deque>
 #include <map>
+#include <thread>
 #include <new>
 #include <unordered_map>
 #include <vector>
@@ -358,6 +361,246 @@ int inet_server_net_bytes(const inet_server *s, int32_t n_agents, int32_t n_eqs,
   *bytes = (int64_t)(P.bytes + al(4 * (size_t)n_agents + 4) + al(8 * (size_t)n_agents + 8) +
                      al(8 * (size_t)n_eqs + 8));
   return INET_OK;
+}
+
+int inet_server_run(inet_server *s, int32_t n_pool, const int32_t *label, const int32_t *port,
+                    const int64_t *agent_off, const int32_t *eq_lhs, const int32_t *eq_rhs,
+                    const int64_t *eq_off, const int32_t *n_names, const int64_t *agent_cap,
+                    const int64_t *name_cap, int64_t n_req, const double *arrival_s,
+                    const int32_t *pick, uint32_t round_steps, double time_limit_s,
+                    hipStream_t stream, double *done_s, int32_t *status, uint64_t *interactions,
+                    uint32_t *steps, inet_serve_stats *stats) {
+  if (!s || n_pool <= 0 || n_req < 0 || !agent_off || !eq_off || !n_names || round_steps == 0)
+    return INET_EINVAL;
+  if (n_req > 0 && (!arrival_s || !pick || !done_s || !status || !interactions || !steps))
+    return INET_EINVAL;
+  if (!s->running.empty() || !s->finished.empty() || s->round_in_flight) return INET_EINVAL;
+  const CompiledRules &R = s->rules;
+  const int64_t A = agent_off[n_pool], E = eq_off[n_pool];
+  if (agent_off[0] != 0 || eq_off[0] != 0 || (A && (!label || !port)) || (E && (!eq_lhs || !eq_rhs)))
+    return INET_EINVAL;
+  for (int64_t i = 0; i < n_req; i++) {
+    if (pick[i] < 0 || pick[i] >= n_pool) return INET_EINVAL;
+    if (i && arrival_s[i] < arrival_s[i - 1]) return INET_EINVAL;
+  }
+  // validate the pool once
+  for (int32_t j = 0; j < n_pool; j++) {
+    const int64_t a0 = agent_off[j], na = agent_off[j + 1] - a0;
+    const int64_t e0 = eq_off[j], ne = eq_off[j + 1] - e0;
+    if (na < 0 || ne < 0 || na > INT32_MAX || ne > INT32_MAX) return INET_EINVAL;
+    std::vector<int32_t> iface;
+    int rc = validate_net(R, label + a0, port + 2 * a0, na, eq_lhs + e0, eq_rhs + e0, ne,
+                          n_names[j], &iface);
+    if (rc) return rc;
+  }
+  // the pool's initial images and the admission records stay resident for the run
+  const int32_t M = s->max_slots;
+  const size_t img_bytes = al(4 * (size_t)A + 4) + al(8 * (size_t)A + 8) + al(8 * (size_t)E + 8) +
+                           al(sizeof(AdmitRec) * (size_t)M * 2);
+  size_t img_off = 0;
+  if (!take_range(s, img_bytes, &img_off)) return INET_ENOMEM;
+  char *p = s->dev + img_off;
+  auto take = [&](size_t bytes) { char *q = p; p += al(bytes); return q; };
+  int32_t *d_label = (int32_t *)take(4 * (size_t)A + 4);
+  int32_t *d_port = (int32_t *)take(8 * (size_t)A + 8);
+  int32_t *d_eq = (int32_t *)take(8 * (size_t)E + 8);
+  AdmitRec *d_admit = (AdmitRec *)take(sizeof(AdmitRec) * (size_t)M * 2);
+  AdmitRec *h_admit = nullptr;
+  int32_t *h_order = nullptr;
+  NetState *h_states = nullptr;
+  int rc = INET_OK;
+  {
+    std::vector<int32_t> eqs((size_t)2 * E + 2);
+    for (int64_t e = 0; e < E; e++) {
+      eqs[2 * e] = eq_lhs[e];
+      eqs[2 * e + 1] = eq_rhs[e];
+    }
+    hipError_t e = hipSuccess;
+    if (A) e = hipMemcpy(d_label, label, 4 * (size_t)A, hipMemcpyHostToDevice);
+    if (e == hipSuccess && A) e = hipMemcpy(d_port, port, 8 * (size_t)A, hipMemcpyHostToDevice);
+    if (e == hipSuccess && E) e = hipMemcpy(d_eq, eqs.data(), 8 * (size_t)E, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&h_admit, sizeof(AdmitRec) * (size_t)M * 2);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&h_order, 4 * (size_t)M);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&h_states, sizeof(NetState) * (size_t)M);
+    if (e != hipSuccess) rc = INET_EHIP;
+  }
+  std::vector<int64_t> req_of(M, -1);
+  std::vector<int32_t> boost_of(M, 1);
+  std::deque<std::pair<int64_t, int32_t>> retry;  // (request, capacity multiplier)
+  int64_t next = 0, rounds = 0, retries = 0;
+  int32_t max_res = 0, n_admit = 0, buf = 0;
+  using clk = std::chrono::steady_clock;
+  const clk::time_point t0 = clk::now();
+  auto now = [&]() { return std::chrono::duration<double>(clk::now() - t0).count(); };
+  // admit one request into a free slot and byte range: 1 admitted, 0 no room
+  // now, -1 its capacities cannot be planned (too large)
+  auto admit = [&](int64_t req, int32_t boost) -> int {
+    const int32_t j = pick[req];
+    const int64_t a0 = agent_off[j], na = agent_off[j + 1] - a0;
+    const int64_t e0 = eq_off[j], ne = eq_off[j + 1] - e0;
+    NetPlan P;
+    if (!plan_net(na, ne, n_names[j], agent_cap ? agent_cap[j] : 0, name_cap ? name_cap[j] : 0, &P))
+      return -1;
+    if (boost > 1 &&
+        !plan_net(na, ne, n_names[j], P.agent_cap * boost, P.name_cap * boost, &P))
+      return -1;
+    if (s->free_slots.empty()) return 0;
+    size_t off = 0;
+    if (!take_range(s, P.bytes, &off)) return 0;
+    const int32_t si = s->free_slots.back();
+    s->free_slots.pop_back();
+    inet_server::Slot &S = s->slots[si];
+    S = inet_server::Slot();
+    S.state = 1;
+    S.off = off;
+    S.len = P.bytes;
+    char *q = s->dev + off;
+    auto tk = [&](size_t bytes) { char *r = q; q += al(bytes); return r; };
+    NetDesc &D = S.desc;
+    D.label = (int32_t *)tk(4 * (size_t)P.agent_cap);
+    D.port0 = (int32_t *)tk(4 * (size_t)P.agent_cap);
+    D.port1 = (int32_t *)tk(4 * (size_t)P.agent_cap);
+    D.bind = (int32_t *)tk(4 * (size_t)P.name_cap);
+    D.queue0 = (unsigned long long *)tk(8 * (size_t)P.qcap);
+    D.queue1 = (unsigned long long *)tk(8 * (size_t)P.qcap);
+    D.stuck = (unsigned long long *)tk(8 * (size_t)P.scap);
+    D.init_label = d_label + a0;
+    D.init_port = d_port + 2 * a0;
+    D.init_eq = d_eq + 2 * e0;
+    D.per_rule = s->d_per_rule + (size_t)si * R.nr;
+    D.st = s->d_states + si;
+    D.agent_cap = (int32_t)P.agent_cap;
+    D.name_cap = (int32_t)P.name_cap;
+    D.qcap = (int32_t)P.qcap;
+    D.scap = (int32_t)P.scap;
+    D.n_agents0 = (int32_t)na;
+    D.n_eqs0 = (int32_t)ne;
+    D.n_names0 = n_names[j];
+    D.order = si;
+    AdmitRec &rec = h_admit[(size_t)buf * M + n_admit++];
+    rec.desc = D;
+    rec.slot = si;
+    rec.pad = 0;
+    req_of[si] = req;
+    boost_of[si] = boost;
+    s->running.push_back(si);
+    return 1;
+  };
+  auto give_up = [&](int64_t req) {
+    done_s[req] = now();
+    status[req] = INET_ENOMEM;
+    interactions[req] = 0;
+    steps[req] = 0;
+  };
+  // admit requests that have arrived, retries first, in arrival order
+  auto admit_arrived = [&](double t) {
+    while (true) {
+      if (!retry.empty()) {
+        const int a = admit(retry.front().first, retry.front().second);
+        if (a == 0) return;
+        if (a < 0) give_up(retry.front().first);
+        retry.pop_front();
+      } else if (next < n_req && arrival_s[next] <= t) {
+        const int a = admit(next, 1);
+        if (a == 0) return;
+        if (a < 0) give_up(next);
+        next++;
+      } else {
+        return;
+      }
+    }
+  };
+  auto release = [&](int32_t si) {
+    inet_server::Slot &S = s->slots[si];
+    give_range(s, S.off, S.len);
+    S = inet_server::Slot();
+    s->free_slots.push_back(si);
+    req_of[si] = -1;
+  };
+  const int nr = R.nr;
+  while (rc == INET_OK && (next < n_req || !retry.empty() || !s->running.empty())) {
+    const double t = now();
+    if (t > time_limit_s) { rc = INET_ELIMIT; break; }
+    admit_arrived(t);
+    if (s->running.empty()) {
+      if (!retry.empty() || (next < n_req && arrival_s[next] <= t)) { rc = INET_ENOMEM; break; }
+      const double wait = next < n_req ? arrival_s[next] - t : 0.0;
+      if (wait > 5e-4) std::this_thread::sleep_for(std::chrono::duration<double>(wait - 2e-4));
+      continue;
+    }
+    // install this round's admissions with one copy and one launch
+    if (n_admit) {
+      AdmitRec *src = h_admit + (size_t)buf * M, *dst = d_admit + (size_t)buf * M;
+      if (hipMemcpyAsync(dst, src, sizeof(AdmitRec) * (size_t)n_admit, hipMemcpyHostToDevice,
+                         stream) != hipSuccess) { rc = INET_EHIP; break; }
+      rc = launch_admit(dst, n_admit, s->d_descs, nr, stream);
+      if (rc) break;
+      n_admit = 0;
+      buf ^= 1;
+    }
+    const int n = (int)s->running.size();
+    std::copy(s->running.begin(), s->running.end(), h_order);
+    s->order_host = s->running;
+    if (hipMemcpyAsync(s->d_order, h_order, 4 * (size_t)n, hipMemcpyHostToDevice, stream) !=
+        hipSuccess) { rc = INET_EHIP; break; }
+    const LaunchShape sh = effective_shape(s->cfg, n > 1 ? n : 2, R);
+    int grid = 1;
+    rc = resident_grid(sh, R, s->cfg, n, &grid);
+    if (!rc) rc = launch_zero(s->d_counter, 1, stream);
+    if (!rc) rc = launch_reduce(R, sh, grid, s->d_descs, s->d_order, n, s->d_counter, s->d_rules,
+                                round_steps, s->cfg.jump ? FLAG_JUMP : 0, stream);
+    if (rc) break;
+    if (hipMemcpyAsync(h_states, s->d_states, sizeof(NetState) * (size_t)M, hipMemcpyDeviceToHost,
+                       stream) != hipSuccess) { rc = INET_EHIP; break; }
+    rounds++;
+    max_res = std::max(max_res, n);
+    // requests arriving during the round are admitted for the next one
+    admit_arrived(now());
+    if (hipStreamSynchronize(stream) != hipSuccess) { rc = INET_EHIP; break; }
+    const double done = now();
+    std::vector<char> in_round(M, 0);
+    for (int32_t si : s->order_host) in_round[si] = 1;
+    std::vector<int32_t> still;
+    still.reserve(s->running.size());
+    for (int32_t si : s->running) {
+      const NetState &st = h_states[si];
+      if (!in_round[si] || !(st.phase == PHASE_DONE || st.status == ST_ENOMEM ||
+                             st.status == ST_EINTERNAL)) {
+        still.push_back(si);
+        continue;
+      }
+      const int64_t req = req_of[si];
+      const int32_t boost = boost_of[si];
+      release(si);
+      if (st.status == ST_ENOMEM && boost < 4096) {
+        retry.emplace_back(req, boost * 8);
+        retries++;
+        continue;
+      }
+      done_s[req] = done;
+      status[req] = st.status;
+      interactions[req] = st.interactions;
+      steps[req] = st.steps;
+    }
+    s->running.swap(still);
+  }
+  if (rc != INET_OK) {
+    (void)hipStreamSynchronize(stream);
+    for (int32_t si : std::vector<int32_t>(s->running)) release(si);
+    s->running.clear();
+  }
+  s->order_host.clear();
+  if (h_admit) (void)hipHostFree(h_admit);
+  if (h_order) (void)hipHostFree(h_order);
+  if (h_states) (void)hipHostFree(h_states);
+  give_range(s, img_off, img_bytes);
+  if (stats) {
+    stats->rounds = rounds;
+    stats->max_resident = max_res;
+    stats->retries = (int32_t)retries;
+    stats->wall_s = now();
+  }
+  return rc;
 }
 
 void inet_server_free(inet_server *s) {

@@ -7,6 +7,11 @@ on a separate stream, so they overlap the running round), launches a round
 harvests the nets that finished, and records each request's latency
 (completion minus arrival, queueing included).  A request that ran out of its
 capacities is resubmitted with larger ones.
+
+``serve`` runs that loop here (it can keep every normal form, for checks);
+``serve_native`` runs the same loop inside the library (inet_server_run),
+with the request pool resident on the device and each round's admissions
+installed by one launch, which is what the served measurements use.
 """
 from __future__ import annotations
 
@@ -121,3 +126,23 @@ def serve(rules, pool: Sequence, arrivals: np.ndarray, pick: Sequence[int],
     if server is None:
         srv.free()
     return ServeReport(served, wall, rounds, max_res, retries)
+
+
+def serve_native(rules, pool: Sequence, arrivals: np.ndarray, pick: Sequence[int],
+                 caps: Optional[Sequence] = None, max_slots: int = 4096,
+                 workspace_bytes: int = 8 << 30, round_steps: int = 256, wg_size: int = 0,
+                 time_limit: float = 600.0, server: Optional[Server] = None) -> ServeReport:
+    """The serving loop of ``serve`` run by the library (inet_server_run);
+    results carry counters only (no normal forms)."""
+    import torch
+
+    srv = server or Server(rules, max_slots, workspace_bytes)
+    srv.set_config(wg_size=wg_size)
+    out = srv.run(pool, arrivals, pick, caps=caps, round_steps=round_steps,
+                  time_limit=time_limit, stream=torch.cuda.current_stream())
+    served = [Served(int(pick[i]), float(arrivals[i]), float(out["done"][i]), int(out["status"][i]),
+                     int(out["interactions"][i]), int(out["steps"][i]))
+              for i in range(len(pick))]
+    if server is None:
+        srv.free()
+    return ServeReport(served, out["wall"], out["rounds"], out["max_resident"], out["retries"])

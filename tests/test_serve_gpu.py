@@ -9,7 +9,7 @@ import pytest
 import oracle
 import paper_1404_0076_amd as P
 from paper_1404_0076_amd import nets
-from paper_1404_0076_amd.serve import serve
+from paper_1404_0076_amd.serve import serve, serve_native
 
 from closed_forms import small_exprs
 from gpu_util import assert_same, oracle_run
@@ -96,6 +96,45 @@ def test_admission_by_free_bytes_and_retry():
         assert np.array_equal(s.nf, refs[s.index].nf) and s.interactions == refs[s.index].interactions
     assert srv.stats()["free_bytes"] == free0 and srv.stats()["running"] == 0
     srv.free()
+
+
+def test_native_loop_matches_oracle():
+    # the library's own serving loop: every request's status, interaction
+    # count and step count equal the oracle's (steps = its maximal parallel
+    # rounds), on a server that is reused for a second run
+    pool = _pool()
+    refs = [oracle.reduce(R, n, schedule="rounds") for n in pool]
+    caps = [(n.n_agents + 4 * r.interactions + 1024, 4 * (n.n_agents + 4 * r.interactions + 1024))
+            for n, r in zip(pool, refs)]
+    rng = np.random.Generator(np.random.PCG64(11))
+    srv = P.Server(R, 64, 1 << 30)
+    free0 = srv.stats()["free_bytes"]
+    for run in range(2):
+        pick = rng.integers(0, len(pool), 600)
+        arrivals = np.cumsum(rng.exponential(1.0 / 30000.0, len(pick)))
+        say("native serving", run, len(pick), "requests")
+        rep = serve_native(R, pool, arrivals, pick, caps=caps, round_steps=16, server=srv)
+        assert len(rep.served) == len(pick) and rep.rounds > 1
+        for s in rep.served:
+            ref = refs[s.index]
+            assert s.status == ref.status and s.interactions == ref.interactions, s.index
+            assert s.steps == ref.rounds, s.index
+            assert s.done >= s.arrival
+        assert srv.stats()["free_bytes"] == free0 and srv.stats()["running"] == 0
+    srv.free()
+
+
+def test_native_loop_retries_out_of_memory():
+    pool = [n for _, n in small_exprs(12, 12, 5, 20_000, min_count=2_000)]
+    refs = [oracle_run(R, n) for n in pool]
+    caps = [(n.n_agents + 8, n.n_names + 8) for n in pool]
+    pick = np.arange(len(pool))
+    say("native retries", len(pool))
+    rep = serve_native(R, pool, np.zeros(len(pool)), pick, caps=caps, max_slots=8,
+                       workspace_bytes=256 << 20, round_steps=64)
+    assert rep.retries >= 1
+    for s in rep.served:
+        assert s.status == P.OK and s.interactions == refs[s.index].interactions
 
 
 def test_server_rejects_when_full():
