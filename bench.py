@@ -156,6 +156,40 @@ def bench_serve(args, P, R, nets, torch):
     print(json.dumps(out), flush=True)
 
 
+def bench_pipeline(args, P, R, net_list, workload, used_a, used_n, inter, steps, torch):
+    """The paper's own evaluation loop (inet_reduce_pipeline) on the same nets,
+    for comparison with the net engines (an ablation, not the headline)."""
+    # the loop allocates every slot of an iteration before filtering, so give
+    # it room beyond the engines' exact heap needs
+    h = P.batch_load(R, net_list, agent_caps=used_a + 64, name_caps=used_n + 64)
+    for _ in range(args.warmup):
+        h.reset()
+        h.reduce_pipeline()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        h.reset()
+        rs = h.reduce_pipeline()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    bad = [i for i, r in enumerate(rs) if r.status not in (P.OK, P.STUCK)]
+    if bad:
+        raise RuntimeError(f"{len(bad)} nets failed, e.g. net {bad[0]} status {rs[bad[0]].status}")
+    total = int(sum(r.interactions for r in rs))
+    assert total == int(inter.sum()), "the pipeline's interaction count differs from the engine's"
+    out = {
+        "metric": METRIC, "value": total * args.steps / wall, "unit": "interactions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": dict(workload, evaluator="paper pipeline (dummies, filter, sort-based com)",
+                       interactions_per_step=total),
+        "iterations": int(max(r.steps for r in rs)), "engine_steps": int(steps.max()),
+    }
+    h.free()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +218,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true", help="skip the single-net side measurement")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay measurement")
+    ap.add_argument("--pipeline", action="store_true",
+                    help="time the paper's own evaluation loop (ablation) instead of the engine")
     ap.add_argument("--print-kernel-hash", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (to scale HBM counters) and exit")
@@ -252,6 +288,8 @@ def main():
         best = autotune.tune(R, net_list, used_a + 64, used_n + 64, order=order)
         wg, engine = best["wg_size"], best["engine"]
         log(f"autotune: wg {wg} engine {engine}")
+    if args.pipeline:
+        return bench_pipeline(args, P, R, net_list, workload, used_a, used_n, inter, steps, torch)
     h = P.batch_load(R, net_list, agent_caps=used_a + 64, name_caps=used_n + 64)
     h.set_config(wg_size=wg, engine=engine)
     h.set_order(order)

@@ -226,6 +226,22 @@ const char *inet_strerror(int status);
  * events on the launch stream (ms); -1 if not available yet. */
 float inet_last_kernel_ms(inet_net *h);
 
+/* The paper's own evaluation loop (Sections 3.3-3.6), kept as an ablation to
+ * compare the net engines against, on the same nets and GPU: a list of
+ * equations; each iteration applies int to every active pair with a fixed
+ * number of output slots per equation (dummies where the rule leaves fewer),
+ * removes the dummies, then applies com by sorting the equations with a name
+ * side by that name and merging neighbours that share it; it repeats while an
+ * int or a com happened (host-driven, one synchronisation per iteration).
+ * Runs every net of the handle in turn on `stream` and leaves the results as
+ * inet_reduce does (read them with inet_results, inet_readback,
+ * inet_per_rule); `steps` then counts iterations of the loop.  The nets must
+ * be in their loaded state (after loading or inet_reset).  max_iterations 0
+ * means no limit; a net stopped by it reports INET_ELIMIT and cannot be
+ * resumed.  Unlike every other entry point it allocates temporary device
+ * memory (hipMalloc) for its equation lists. */
+int inet_reduce_pipeline(inet_net *h, hipStream_t stream, uint64_t max_iterations);
+
 /* ------------------------------------------------------------------------
  * Continuous batching (serving).  A server owns one caller-provided device
  * buffer and up to max_slots resident nets.  inet_server_submit admits a net

@@ -29,7 +29,7 @@ EXPORTS = [
     "inet_graph_launch", "inet_server_create", "inet_server_set_config", "inet_server_net_bytes",
     "inet_server_submit", "inet_server_step", "inet_server_poll", "inet_server_result",
     "inet_server_per_rule", "inet_server_release", "inet_server_stats", "inet_server_free",
-    "inet_jit_build", "inet_server_run",
+    "inet_jit_build", "inet_server_run", "inet_reduce_pipeline",
 ]
 
 
@@ -91,6 +91,7 @@ def library():
             "inet_server_result": [_P, _I64, _P, _P, _I64, _P],
             "inet_server_per_rule": [_P, _I64, _P, _I32],
             "inet_server_release": [_P, _I64], "inet_server_stats": [_P, _P, _P, _P],
+            "inet_reduce_pipeline": [_P, _P, _U64],
             "inet_server_run": [_P, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _P, _P,
                                 ctypes.c_uint32, ctypes.c_double, _P, _P, _P, _P, _P, _P],
         }
@@ -243,6 +244,12 @@ class Handle:
             raise InetError(rc, "inet_reduce")
         return [Result(r.status, r.n_stuck, r.interactions, r.steps, r.agents_used,
                        r.names_used, r.max_frontier, r.loops) for r in out]
+
+    def reduce_pipeline(self, max_iterations: int = 0, stream=None) -> List[Result]:
+        """The paper's own evaluation loop (inet_reduce_pipeline), for comparison."""
+        s, _ = _stream_handle(stream)
+        self._check(library().inet_reduce_pipeline(self._h, s, max_iterations), "inet_reduce_pipeline")
+        return self.results(stream)
 
     def reset(self, stream=None):
         s, _ = _stream_handle(stream)
