@@ -210,6 +210,8 @@ def main():
     ap.add_argument("--n-nets", type=int, default=4096)
     ap.add_argument("--fib-n", type=int, default=27)
     ap.add_argument("--wg", type=int, default=0)
+    ap.add_argument("--max-resident", type=int, default=0,
+                    help="cap on simultaneously resident net engines (0: as many as fit)")
     ap.add_argument("--engine", type=int, default=0,
                     help="0 default, 1 interpreter, 2 rule-uniform, 3 rules compiled in at load time")
     ap.add_argument("--autotune", action="store_true",
@@ -287,11 +289,12 @@ def main():
         from paper_1404_0076_amd import autotune
         best = autotune.tune(R, net_list, used_a + 64, used_n + 64, order=order)
         wg, engine = best["wg_size"], best["engine"]
-        log(f"autotune: wg {wg} engine {engine}")
+        args.max_resident = best["max_resident"]
+        log(f"autotune: wg {wg} engine {engine} max_resident {args.max_resident}")
     if args.pipeline:
         return bench_pipeline(args, P, R, net_list, workload, used_a, used_n, inter, steps, torch)
     h = P.batch_load(R, net_list, agent_caps=used_a + 64, name_caps=used_n + 64)
-    h.set_config(wg_size=wg, engine=engine)
+    h.set_config(wg_size=wg, engine=engine, max_resident=args.max_resident)
     h.set_order(order)
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
@@ -333,6 +336,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic", "config": dict(workload, wg_size=wg, engine=h.get_config()["engine"],
+                                            max_resident=args.max_resident,
                                             interactions_per_step=total),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

@@ -20,7 +20,8 @@ from . import batch_load
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 WIDTHS = (64, 128, 256, 512, 1024)
-ENGINES = (1, 2)
+ENGINES = (2, 3)  # rule-uniform, and the rule table compiled in (engine 1 is never faster)
+RESIDENTS = (0, 256)  # as many engines as fit, or one per compute unit
 
 
 def workload_signature(net_list: Sequence) -> str:
@@ -47,12 +48,13 @@ def _time(h, reps: int) -> float:
 
 
 def tune(rules, net_list: Sequence, agent_caps, name_caps, order=None, reps: int = 2,
-         widths=WIDTHS, engines=ENGINES, residents=(0,), cache: Optional[str] = CACHE,
+         widths=WIDTHS, engines=ENGINES, residents=RESIDENTS, cache: Optional[str] = CACHE,
          verbose: bool = False) -> Dict:
     """Best {"wg_size", "engine", "max_resident", "seconds"} for this workload."""
     import torch
     dev = torch.cuda.get_device_name(0)
-    key = f"{dev}/{workload_signature(net_list)}/{len(net_list)}"
+    key = (f"{dev}/{workload_signature(net_list)}/{len(net_list)}/"
+           f"{'-'.join(map(str, widths))}/{'-'.join(map(str, engines))}/{'-'.join(map(str, residents))}")
     if cache and os.path.exists(cache):
         with open(cache) as f:
             table = json.load(f)

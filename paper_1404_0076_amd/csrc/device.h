@@ -115,17 +115,18 @@ __device__ __forceinline__ int xchg(gint *p, int v) {
 // com: resolve the equation u = v.  Returns true with (ou, ov) when it ends
 // as an equation between two agents (a new active pair).  Every exchange that
 // finds a filled cell consumes both occurrences of that name, so a chain is
-// at most as long as the number of names; the guard only turns a broken
-// invariant into an error instead of a spin.
-__device__ __forceinline__ bool link(int u, int v, gint *__restrict__ bind, int &ou, int &ov,
-                                     int &loops, int *status) {
+// at most as long as the number of names; the guards only turn a broken
+// invariant (an endless chain, a name outside the net's cells) into an error
+// instead of a spin or a stray access.
+__device__ __forceinline__ bool link(int u, int v, gint *__restrict__ bind, unsigned name_cap,
+                                     int &ou, int &ov, int &loops, int *status) {
   for (int guard = 0;; guard++) {
     if (u >= 0) {
       if (v >= 0) { ou = u; ov = v; return true; }
       const int t = u; u = v; v = t;
     }
     if (u == v) { loops++; return false; }  // x = x: closed loop
-    if (guard > (1 << 24)) { *status = ST_EINTERNAL; return false; }
+    if (guard > (1 << 24) || (unsigned)~u >= name_cap) { *status = ST_EINTERNAL; return false; }
     const int old = xchg(at(bind, (unsigned)~u), v);
     if (old == EMPTY) return false;         // first occurrence: parked
     u = old;                                // second: old = v
@@ -272,7 +273,7 @@ __device__ __forceinline__ void pass_interp(INET_PASS_ARGS) {
       const int u = eu[j], v = ev[j];
       if (u >= 0) { prod = true; ou = u; ov = v; }
       else if (u == v) loops++;
-      else if (eo[j] != EMPTY) prod = link(eo[j], v, bind, ou, ov, loops, s_status);
+      else if (eo[j] != EMPTY) prod = link(eo[j], v, bind, (unsigned)D.name_cap, ou, ov, loops, s_status);
     }
     wave_push(prod, ou, ov, nq_l, QCAP, nq_g, D.qcap, ncnt, s_status);
   }
@@ -304,7 +305,7 @@ __device__ __forceinline__ void finish_links(int lneq, int (&eu)[MAXL], int (&ev
     }
     const bool chain = has && u < 0 && u != v && o != EMPTY && !(o >= 0 && v >= 0);
     if (ballot(chain)) {
-      if (chain) prod[j] = link(o, v, bind, ou[j], ov[j], loops, s_status);
+      if (chain) prod[j] = link(o, v, bind, (unsigned)D.name_cap, ou[j], ov[j], loops, s_status);
     }
   }
   // append all new pairs of the wave with one LDS atomic
@@ -592,7 +593,8 @@ __device__ __forceinline__ void issue_links(const Lane &L, gint *bind, int (&eo)
 // a parked side, a closed loop, or a chain (the exchange met a parked name:
 // com carries on along it)
 template <int R, int J, int MAXL>
-__device__ __forceinline__ void decide_links(const Lane &L, gint *bind, const int (&eo)[MAXL],
+__device__ __forceinline__ void decide_links(const Lane &L, gint *bind, unsigned name_cap,
+                                             const int (&eo)[MAXL],
                                              int (&pu)[MAXL], int (&pv)[MAXL], int &loops,
                                              bool &bad) {
   if constexpr (J < rt::T[R][RT_NEQ] && J < MAXL) {
@@ -622,14 +624,14 @@ __device__ __forceinline__ void decide_links(const Lane &L, gint *bind, const in
         if (chain) {
           int ou = -1, ov = 0;
           int guard = 0;
-          if (!link(o, v, bind, ou, ov, loops, &guard)) ou = -1;
+          if (!link(o, v, bind, name_cap, ou, ov, loops, &guard)) ou = -1;
           if (guard) bad = true;
           pu[J] = ou;
           pv[J] = ov;
         }
       }
     }
-    decide_links<R, J + 1, MAXL>(L, bind, eo, pu, pv, loops, bad);
+    decide_links<R, J + 1, MAXL>(L, bind, name_cap, eo, pu, pv, loops, bad);
   }
 }
 
@@ -661,7 +663,9 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
     }
   }
   const bool act = valid && code >= 0;
-  const int rid = act ? (code >> 1) : -1;
+  // the lane's rule; -1 when it has none, or when its group could not be
+  // allocated (the second walk then leaves it alone)
+  int rid = act ? (code >> 1) : -1;
   Lane L;
   L.a = a; L.b = b; L.pa0 = pa0; L.pa1 = pa1; L.pb0 = pb0; L.pb1 = pb1;
   L.my_a = 0; L.my_n = 0;
@@ -672,6 +676,8 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
   }
   // exchange results, one register per (rule, link): exchanges of different
   // rules are then in flight together without write-after-write waits
+  // (written by the first walk for every lane of the rule's group, and read
+  // by the second walk only for those lanes)
   int eo[rt::NR > 0 ? rt::NR : 1][MAXL];
   int pu[MAXL], pv[MAXL];  // new active pair of link j, pu[j] < 0 if none
 #pragma unroll
@@ -689,7 +695,10 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
       if (lane == lead) atomicAdd(&s_rc[R], (unsigned long long)cnt);
       if ((nalloc > 0 && ba + nalloc * cnt > D.agent_cap) ||
           (nfresh > 0 && bn + nfresh * cnt > D.name_cap)) {
+        // out of heap: the step ends with ENOMEM; these lanes issue nothing,
+        // and their exchange results are never read
         C.fail_uniform(lane, lead);
+        if (mine) rid = -1;
         return;
       }
       if (mine) {
@@ -710,7 +719,8 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
   bool bad = false;
   for_rules<0>(rid, [&](auto ic, unsigned long long) {
     constexpr int R = decltype(ic)::value;
-    if (rid == R) decide_links<R, 0, MAXL>(opaque(L), bind, eo[R], pu, pv, loops, bad);
+    if (rid == R)
+      decide_links<R, 0, MAXL>(opaque(L), bind, (unsigned)D.name_cap, eo[R], pu, pv, loops, bad);
   });
   // append the wave's new active pairs
   unsigned long long m[MAXL];
@@ -831,7 +841,7 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
         Pair e = mkpair(0, 0);
         if (valid) e = unpk(queue0[i]);
         int ou = 0, ov = 0, loops = 0;
-        const bool prod = valid && link(e.x, e.y, bind, ou, ov, loops, &s_status);
+        const bool prod = valid && link(e.x, e.y, bind, (unsigned)D.name_cap, ou, ov, loops, &s_status);
         wave_push(prod, ou, ov, q[1], QCAP, queue1, D.qcap, &s_cnt[1], &s_status);
         if (loops) atomicAdd(&s_loops, loops);
       }

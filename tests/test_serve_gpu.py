@@ -166,13 +166,14 @@ def test_autotune_picks_a_valid_shape(tmp_path):
     cache = str(tmp_path / "tune.json")
     best = autotune.tune(R, batch, caps, [4 * c for c in caps], reps=1, widths=(64, 256),
                          cache=cache)
-    assert best["wg_size"] in (64, 256) and best["engine"] in (1, 2)
-    assert len(best["trials"]) == 4
-    again = autotune.tune(R, batch, caps, [4 * c for c in caps], cache=cache)
+    assert best["wg_size"] in (64, 256) and best["engine"] in (2, 3)
+    assert best["max_resident"] in autotune.RESIDENTS
+    assert len(best["trials"]) == 2 * len(autotune.ENGINES) * len(autotune.RESIDENTS)
+    again = autotune.tune(R, batch, caps, [4 * c for c in caps], widths=(64, 256), cache=cache)
     assert again["wg_size"] == best["wg_size"] and again["engine"] == best["engine"]
     # the tuned shape still gives the oracle's results
     h = P.batch_load(R, batch, agent_caps=caps, name_caps=[4 * c for c in caps])
-    h.set_config(wg_size=best["wg_size"], engine=best["engine"])
+    h.set_config(wg_size=best["wg_size"], engine=best["engine"], max_resident=best["max_resident"])
     rs = h.reduce()
     for i in range(len(batch)):
         assert_same((rs[i], h.readback(i), h.per_rule(i)), refs[i], f"tuned net {i}")
