@@ -127,7 +127,7 @@ def bench_serve(args, P, R, nets, torch):
     from paper_1404_0076_amd.serve import serve, serve_native
     pool = nets.config5_pool(seed=2, n_nets=args.pool)
     log(f"sizing pool of {len(pool)}")
-    used_a, used_n, steps, inter = size_batch(P, R, pool, args.wg or 256)
+    used_a, used_n, steps, inter = size_batch(P, R, pool, args.wg or 64)
     caps = list(zip(used_a + 64, used_n + 64))
     arrivals = nets.poisson_arrivals(3, args.rate, args.duration)
     rng = np.random.Generator(np.random.PCG64(4))
@@ -210,8 +210,9 @@ def main():
     ap.add_argument("--n-nets", type=int, default=4096)
     ap.add_argument("--fib-n", type=int, default=27)
     ap.add_argument("--wg", type=int, default=0)
-    ap.add_argument("--max-resident", type=int, default=0,
-                    help="cap on simultaneously resident net engines (0: as many as fit)")
+    ap.add_argument("--max-resident", type=int, default=-1,
+                    help="cap on simultaneously resident net engines (0: as many as fit; "
+                         "default: one per compute unit for a batch)")
     ap.add_argument("--engine", type=int, default=0,
                     help="0 default, 1 interpreter, 2 rule-uniform, 3 rules compiled in at load time")
     ap.add_argument("--autotune", action="store_true",
@@ -280,7 +281,13 @@ def main():
         net_list = [nets.config1_add_tree(args.seed)]
         workload = {"workload": f"single net: balanced Add tree over 1024 numerals in [0,256), "
                                 f"seed {args.seed}"}
-    wg = args.wg or (256 if len(net_list) > 1 else 1024)
+    wg = args.wg or (64 if len(net_list) > 1 else 1024)
+    if args.max_resident < 0:
+        # batch: one engine per compute unit (the longest net's engine then has
+        # its CU to itself; the other engines still finish the rest within its
+        # critical path); single nets: not applicable
+        n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+        args.max_resident = n_cu if len(net_list) > 1 else 0
     log(f"sizing {len(net_list)} nets (wg {wg})")
     used_a, used_n, steps, inter = size_batch(P, R, net_list, wg, args.engine)
     order = np.argsort(-steps, kind="stable").astype(np.int32)  # longest critical path first
