@@ -428,13 +428,16 @@ struct IC {
 // the rule code of every rule present among the wave's lanes, in rule order:
 // straight-line code (one ballot per rule), so values produced for one rule
 // (exchange results in flight) are not copied around a loop, which would wait
-// for them
+// for them; `rest` holds the lanes not handled yet, and the walk stops when
+// none is left
 template <int R, class F>
-__device__ __forceinline__ void for_rules(int rid, F &&f) {
+__device__ __forceinline__ void for_rules(int rid, unsigned long long rest, F &&f) {
   if constexpr (R < rt::NR) {
-    const unsigned long long gm = ballot(rid == R);
-    if (gm) f(IC<R>{}, gm);
-    for_rules<R + 1>(rid, f);
+    if (rest) {
+      const unsigned long long gm = ballot(rid == R);
+      if (gm) f(IC<R>{}, gm);
+      for_rules<R + 1>(rid, rest & ~gm, f);
+    }
   }
 }
 
@@ -641,7 +644,7 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
                                             gint *label, gint *port0, gint *port1, gint *bind,
                                             gint2 *stuck, const int *rule_of, Pair *nq_l,
                                             gint2 *nq_g, Ctr<SOLO> &C, int *s_loops,
-                                            unsigned long long *s_rc) {
+                                            unsigned &rc_lane) {
   const int lane = __lane_id();
   const int code = rule_of[valid ? la * rt::NS + lb : 0];
   // take the loaded ports through a copy on every path: later rule blocks then
@@ -683,7 +686,7 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
 #pragma unroll
   for (int j = 0; j < MAXL; j++) { pu[j] = -1; pv[j] = 0; }
   // first walk: allocate, write the new agents, issue the exchanges
-  for_rules<0>(rid, [&](auto ic, unsigned long long gm) {
+  for_rules<0>(rid, ballot(rid >= 0), [&](auto ic, unsigned long long gm) {
       constexpr int R = decltype(ic)::value;
       constexpr int nalloc = rt::T[R][RT_NALLOC], nfresh = rt::T[R][RT_NFRESH];
       const int lead = __builtin_ctzll(gm);
@@ -692,7 +695,8 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
       int ba = 0, bn = 0;
       if constexpr (nalloc > 0) ba = C.agents(nalloc * cnt, lane, lead);
       if constexpr (nfresh > 0) bn = C.names(nfresh * cnt, lane, lead);
-      if (lane == lead) atomicAdd(&s_rc[R], (unsigned long long)cnt);
+      // interactions per rule: lane R of the wave counts rule R
+      rc_lane += lane == R ? (unsigned)cnt : 0u;
       if ((nalloc > 0 && ba + nalloc * cnt > D.agent_cap) ||
           (nfresh > 0 && bn + nfresh * cnt > D.name_cap)) {
         // out of heap: the step ends with ENOMEM; these lanes issue nothing,
@@ -717,7 +721,7 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
   // second walk: decide every link
   int loops = 0;
   bool bad = false;
-  for_rules<0>(rid, [&](auto ic, unsigned long long) {
+  for_rules<0>(rid, ballot(rid >= 0), [&](auto ic, unsigned long long) {
     constexpr int R = decltype(ic)::value;
     if (rid == R)
       decide_links<R, 0, MAXL>(opaque(L), bind, (unsigned)D.name_cap, eo[R], pu, pv, loops, bad);
@@ -868,6 +872,7 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
         C.next = 0;
         int n = __builtin_amdgcn_readfirstlane(s_cnt[ci]);
         int maxf = __builtin_amdgcn_readfirstlane(s_maxf);
+        unsigned rc_lane = 0;  // lane r: interactions of rule r in this launch
         while (n > 0 && C.err >= 0 && steps < stop) {
           if (n > maxf) maxf = n;
           const Pair *cq_l = q[cur];
@@ -882,7 +887,7 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
                                  lb, pa0, pa1, pb0, pb1);
             pass_static<QCAP, MAXL, true>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, label, port0,
                                           port1, bind, stuck, rule_of, nq_l, nq_g, C, &s_loops,
-                                          s_rc);
+                                          rc_lane);
           }
           // lanes of one wave need no cache action or wait to see each
           // other's writes (wavefront scope); the fence only keeps the
@@ -892,6 +897,7 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
           cur ^= 1;
           n = C.next;
         }
+        if (rc_lane) atomicAdd(&s_rc[tid], (unsigned long long)rc_lane);
         __syncthreads();
         if (tid == 0) {
           s_cnt[ci] = n;
@@ -908,6 +914,7 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
         C.name_top = &s_name_top;
         C.nstuck = &s_nstuck;
         C.status = &s_status;
+        unsigned rc_lane = 0;  // lane r of each wave: interactions of rule r
         for (;;) {
           __syncthreads();
           const int n = s_cnt[ci];
@@ -930,12 +937,14 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
                                  lb, pa0, pa1, pb0, pb1);
             pass_static<QCAP, MAXL, false>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, label,
                                            port0, port1, bind, stuck, rule_of, nq_l, nq_g, C,
-                                           &s_loops, s_rc);
+                                           &s_loops, rc_lane);
           }
           steps++;
           cur ^= 1;
           ci = cn;
         }
+        if (rc_lane) atomicAdd(&s_rc[__lane_id()], (unsigned long long)rc_lane);
+        __syncthreads();
       }
     } else
 #endif

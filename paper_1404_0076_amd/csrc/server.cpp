@@ -98,6 +98,14 @@ void give_range(inet_server *s, size_t off, size_t len) {
   }
 }
 
+// a round runs every resident net for a bounded number of steps, so a wide
+// frontier must not make the round long: engines of 256 lanes unless the
+// caller chose a width
+inet_config serving_config(inet_config cfg) {
+  if (cfg.wg_size == 0) cfg.wg_size = 256;
+  return cfg;
+}
+
 inet_server::Slot *slot_of(inet_server *s, int64_t ticket) {
   auto it = s->by_ticket.find(ticket);
   if (it == s->by_ticket.end()) return nullptr;
@@ -244,9 +252,10 @@ int inet_server_step(inet_server *s, hipStream_t stream, uint32_t max_steps) {
   const int n = (int)s->running.size();
   s->order_host = s->running;
   HIPCHK(hipMemcpyAsync(s->d_order, s->order_host.data(), 4 * (size_t)n, hipMemcpyHostToDevice, stream));
-  const LaunchShape sh = effective_shape(s->cfg, n > 1 ? n : 2, s->rules);
+  const inet_config cfg = serving_config(s->cfg);
+  const LaunchShape sh = effective_shape(cfg, n > 1 ? n : 2, s->rules);
   int grid = 1;
-  int rc = resident_grid(sh, s->rules, s->cfg, n, &grid);
+  int rc = resident_grid(sh, s->rules, cfg, n, &grid);
   if (rc) return rc;
   rc = launch_zero(s->d_counter, 1, stream);
   if (rc) return rc;
@@ -543,9 +552,10 @@ int inet_server_run(inet_server *s, int32_t n_pool, const int32_t *label, const 
     s->order_host = s->running;
     if (hipMemcpyAsync(s->d_order, h_order, 4 * (size_t)n, hipMemcpyHostToDevice, stream) !=
         hipSuccess) { rc = INET_EHIP; break; }
-    const LaunchShape sh = effective_shape(s->cfg, n > 1 ? n : 2, R);
+    const inet_config cfg = serving_config(s->cfg);
+    const LaunchShape sh = effective_shape(cfg, n > 1 ? n : 2, R);
     int grid = 1;
-    rc = resident_grid(sh, R, s->cfg, n, &grid);
+    rc = resident_grid(sh, R, cfg, n, &grid);
     if (!rc) rc = launch_zero(s->d_counter, 1, stream);
     if (!rc) rc = launch_reduce(R, sh, grid, s->d_descs, s->d_order, n, s->d_counter, s->d_rules,
                                 round_steps, s->cfg.jump ? FLAG_JUMP : 0, stream);
