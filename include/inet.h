@@ -51,8 +51,9 @@
  *
  * Device memory: every handle lives in ONE caller-provided device buffer
  * (e.g. a torch uint8 tensor); size it with inet_workspace_bytes.  The
- * library never allocates device memory itself except a small pinned host
- * staging area; the buffer must outlive the handle.
+ * library never allocates device memory itself except small pinned host
+ * staging areas (and the paper-pipeline ablation, inet_reduce_pipeline, which
+ * allocates temporary device memory); the buffer must outlive the handle.
  *
  * Streams: the *_async entry points enqueue work on the caller's stream and
  * return at once; inet_results synchronises that stream.  A handle is not
@@ -133,8 +134,8 @@ typedef struct inet_net inet_net;
 
 /* Workspace bytes for n_nets nets.  agent_cap[i] / name_cap[i]: capacity of
  * net i's agent heap and name cells (>= its initial size; 0 = a default of 4x
- * the initial size plus 1024).  n_eqs[i], n_agents[i], n_names[i]: initial
- * sizes. */
+ * the initial size plus 1024; at most 2^28 - 16 agents and 2^29 - 16 names,
+ * else INET_EINVAL).  n_eqs[i], n_agents[i], n_names[i]: initial sizes. */
 int inet_workspace_bytes(const inet_rules *rules, int32_t n_nets, const int64_t *n_agents,
                          const int64_t *n_eqs, const int32_t *n_names, const int64_t *agent_cap,
                          const int64_t *name_cap, size_t *bytes);

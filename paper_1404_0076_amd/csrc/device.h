@@ -68,6 +68,22 @@ __device__ __forceinline__ gint *at(gint *base, unsigned idx) {
   return (gint *)((gchar *)base + (idx << 2));
 }
 
+// an agent is one 16-byte record {label, port 0, port 1, unused}: one load or
+// store moves a whole agent, and a record never straddles a cache line
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) v4i gv4i;
+__device__ __forceinline__ gv4i *rec(gint *agent, unsigned idx) {
+  return (gv4i *)((gchar *)agent + (idx << 4));
+}
+__device__ __forceinline__ v4i mkrec(int label, int p0, int p1) {
+  v4i r;
+  r.x = label;
+  r.y = p0;
+  r.z = p1;
+  r.w = 0;
+  return r;
+}
+
 __device__ __forceinline__ int count_below(unsigned long long m) {
   return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
                                         __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
@@ -182,7 +198,7 @@ __device__ __forceinline__ void jump_cells(gint *__restrict__ bind, int lo, int 
 // lane (ENGINE 1)
 #define INET_PASS_ARGS                                                                    \
   bool valid, int a, int b, int la, int lb, int pa0, int pa1, int pb0, int pb1, const NetDesc &D, \
-      gint *label, gint *port0, gint *port1, gint *bind, gint2 *stuck, const int *rule_of,        \
+      gint *agent, gint *bind, gint2 *stuck, const int *rule_of,                                 \
       const int *templ, const int *arity, const int *__restrict__ g_templ,                          \
       const int *__restrict__ g_arity, int ns, Pair *nq_l, gint2 *nq_g, int *ncnt, int *s_status,  \
       int *s_agent_top, int *s_name_top, int *s_nstuck, int *s_loops, unsigned long long *s_rc
@@ -239,10 +255,10 @@ __device__ __forceinline__ void pass_interp(INET_PASS_ARGS) {
     for (int kk = 0; kk < nnew; kk++) {
       const int slot = kk == 0 ? a : (kk == 1 ? b : my_a + kk - 2);
       const int L = T[RT_LABEL + kk];
-      *at(label, (unsigned)slot) = L;
       const int ar = arity[L];
-      if (ar > 0) *at(port0, (unsigned)slot) = resolve(T[RT_PORT + 2 * kk], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
-      if (ar > 1) *at(port1, (unsigned)slot) = resolve(T[RT_PORT + 2 * kk + 1], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
+      const int q0 = ar > 0 ? resolve(T[RT_PORT + 2 * kk], a, b, pa0, pa1, pb0, pb1, my_a, my_n) : 0;
+      const int q1 = ar > 1 ? resolve(T[RT_PORT + 2 * kk + 1], a, b, pa0, pa1, pb0, pb1, my_a, my_n) : 0;
+      *rec(agent, (unsigned)slot) = mkrec(L, q0, q1);
     }
     for (int f = 0; f < nfresh; f++) *at(bind, (unsigned)(my_n + f)) = EMPTY;
     atomicAdd(&s_rc[rid], 1ull);
@@ -386,10 +402,10 @@ __device__ __forceinline__ void pass_uniform(INET_PASS_ARGS) {
       for (int kk = 0; kk < nnew; kk++) {
         const int slot = kk == 0 ? a : (kk == 1 ? b : my_a + kk - 2);
         const int L = T[RT_LABEL + kk];
-        *at(label, (unsigned)slot) = L;
         const int ar = g_arity[L];
-        if (ar > 0) *at(port0, (unsigned)slot) = resolve_u(T[RT_PORT + 2 * kk], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
-        if (ar > 1) *at(port1, (unsigned)slot) = resolve_u(T[RT_PORT + 2 * kk + 1], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
+        const int q0 = ar > 0 ? resolve_u(T[RT_PORT + 2 * kk], a, b, pa0, pa1, pb0, pb1, my_a, my_n) : 0;
+        const int q1 = ar > 1 ? resolve_u(T[RT_PORT + 2 * kk + 1], a, b, pa0, pa1, pb0, pb1, my_a, my_n) : 0;
+        *rec(agent, (unsigned)slot) = mkrec(L, q0, q1);
       }
       for (int f = 0; f < nfresh; f++) *at(bind, (unsigned)(my_n + f)) = EMPTY;
       lneq = neq;
@@ -541,15 +557,16 @@ struct Ctr<false> {
 };
 
 template <int R, int K>
-__device__ __forceinline__ void st_agents(const Lane &L, gint *label, gint *port0, gint *port1) {
+__device__ __forceinline__ void st_agents(const Lane &L, gint *agent) {
   if constexpr (K < rt::T[R][RT_NNEW]) {
     constexpr int LB = rt::T[R][RT_LABEL + K];
     const unsigned slot =
         K == 0 ? (unsigned)L.a : (K == 1 ? (unsigned)L.b : (unsigned)(L.my_a + K - 2));
-    *at(label, slot) = LB;
-    if constexpr (rt::ARITY[LB] > 0) *at(port0, slot) = opnd<rt::T[R][RT_PORT + 2 * K]>(L);
-    if constexpr (rt::ARITY[LB] > 1) *at(port1, slot) = opnd<rt::T[R][RT_PORT + 2 * K + 1]>(L);
-    st_agents<R, K + 1>(L, label, port0, port1);
+    int q0 = 0, q1 = 0;
+    if constexpr (rt::ARITY[LB] > 0) q0 = opnd<rt::T[R][RT_PORT + 2 * K]>(L);
+    if constexpr (rt::ARITY[LB] > 1) q1 = opnd<rt::T[R][RT_PORT + 2 * K + 1]>(L);
+    *rec(agent, slot) = mkrec(LB, q0, q1);
+    st_agents<R, K + 1>(L, agent);
   }
 }
 
@@ -641,7 +658,7 @@ __device__ __forceinline__ void decide_links(const Lane &L, gint *bind, unsigned
 template <int QCAP, int MAXL, bool SOLO>
 __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, int lb, int pa0,
                                             int pa1, int pb0, int pb1, const NetDesc &D,
-                                            gint *label, gint *port0, gint *port1, gint *bind,
+                                            gint *agent, gint *bind,
                                             gint2 *stuck, const int *rule_of, Pair *nq_l,
                                             gint2 *nq_g, Ctr<SOLO> &C, int *s_loops,
                                             unsigned &rc_lane) {
@@ -695,8 +712,9 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
       int ba = 0, bn = 0;
       if constexpr (nalloc > 0) ba = C.agents(nalloc * cnt, lane, lead);
       if constexpr (nfresh > 0) bn = C.names(nfresh * cnt, lane, lead);
-      // interactions per rule: lane R of the wave counts rule R
-      rc_lane += lane == R ? (unsigned)cnt : 0u;
+      // interactions per rule: lane R of the wave counts rule R (the lane id
+      // is opaque so that the test is not hoisted, per rule, out of the loop)
+      rc_lane += opaque(lane) == R ? (unsigned)cnt : 0u;
       if ((nalloc > 0 && ba + nalloc * cnt > D.agent_cap) ||
           (nfresh > 0 && bn + nfresh * cnt > D.name_cap)) {
         // out of heap: the step ends with ENOMEM; these lanes issue nothing,
@@ -712,7 +730,7 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
         X.my_n = bn + nfresh * rank;
         L.my_a = X.my_a;
         L.my_n = X.my_n;
-        st_agents<R, 0>(X, label, port0, port1);
+        st_agents<R, 0>(X, agent);
 #pragma unroll
         for (int f = 0; f < nfresh; f++) *at(bind, (unsigned)(X.my_n + f)) = EMPTY;
         issue_links<R, 0, MAXL>(X, bind, eo[R]);
@@ -756,8 +774,8 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
 // need no branch
 template <int WG, int QCAP>
 __device__ __forceinline__ void fetch_pair(int base, int n, int tid, const Pair *cq_l,
-                                           const gint2 *cq_g, gint *label, gint *port0,
-                                           gint *port1, bool &valid, int &a, int &b, int &la,
+                                           const gint2 *cq_g, gint *agent, bool &valid, int &a,
+                                           int &b, int &la,
                                            int &lb, int &pa0, int &pa1, int &pb0, int &pb1) {
   const int i = base + tid;
   valid = i < n;
@@ -771,12 +789,13 @@ __device__ __forceinline__ void fetch_pair(int base, int n, int tid, const Pair 
   if (!valid) rx = mkpair(0, 0);
   a = rx.x;
   b = rx.y;
-  la = *at(label, (unsigned)a);
-  lb = *at(label, (unsigned)b);
-  pa0 = *at(port0, (unsigned)a);
-  pa1 = *at(port1, (unsigned)a);
-  pb0 = *at(port0, (unsigned)b);
-  pb1 = *at(port1, (unsigned)b);
+  const v4i ra = *rec(agent, (unsigned)a), rb = *rec(agent, (unsigned)b);
+  la = ra.x;
+  pa0 = ra.y;
+  pa1 = ra.z;
+  lb = rb.x;
+  pb0 = rb.y;
+  pb1 = rb.z;
 }
 #endif  // INET_STATIC_RULES
 
@@ -809,9 +828,7 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
     if (k >= n_nets) break;
     const NetDesc D = descs[order[k]];
     NetState *st = D.st;
-    gint *const label = (gint *)D.label;
-    gint *const port0 = (gint *)D.port0;
-    gint *const port1 = (gint *)D.port1;
+    gint *const agent = (gint *)D.agent;
     gint *const bind = (gint *)D.bind;
     gint2 *const queue0 = (gint2 *)D.queue0;
     gint2 *const queue1 = (gint2 *)D.queue1;
@@ -883,10 +900,10 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
           for (int base = 0; base < n; base += WG) {
             bool valid;
             int a, b, la, lb, pa0, pa1, pb0, pb1;
-            fetch_pair<WG, QCAP>(base, n, tid, cq_l, cq_g, label, port0, port1, valid, a, b, la,
-                                 lb, pa0, pa1, pb0, pb1);
-            pass_static<QCAP, MAXL, true>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, label, port0,
-                                          port1, bind, stuck, rule_of, nq_l, nq_g, C, &s_loops,
+            fetch_pair<WG, QCAP>(base, n, tid, cq_l, cq_g, agent, valid, a, b, la, lb, pa0, pa1,
+                                 pb0, pb1);
+            pass_static<QCAP, MAXL, true>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, agent, bind,
+                                          stuck, rule_of, nq_l, nq_g, C, &s_loops,
                                           rc_lane);
           }
           // lanes of one wave need no cache action or wait to see each
@@ -933,10 +950,10 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
           for (int base = 0; base < n; base += WG) {
             bool valid;
             int a, b, la, lb, pa0, pa1, pb0, pb1;
-            fetch_pair<WG, QCAP>(base, n, tid, cq_l, cq_g, label, port0, port1, valid, a, b, la,
-                                 lb, pa0, pa1, pb0, pb1);
-            pass_static<QCAP, MAXL, false>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, label,
-                                           port0, port1, bind, stuck, rule_of, nq_l, nq_g, C,
+            fetch_pair<WG, QCAP>(base, n, tid, cq_l, cq_g, agent, valid, a, b, la, lb, pa0, pa1,
+                                 pb0, pb1);
+            pass_static<QCAP, MAXL, false>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, agent,
+                                           bind, stuck, rule_of, nq_l, nq_g, C,
                                            &s_loops, rc_lane);
           }
           steps++;
@@ -977,16 +994,17 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
         if (!valid) rx = mkpair(0, 0);
         const int a = rx.x, b = rx.y;
         const unsigned ua = (unsigned)a, ub = (unsigned)b;
-        const int la = *at(label, ua), lb = *at(label, ub);
-        const int pa0 = *at(port0, ua), pa1 = *at(port1, ua);
-        const int pb0 = *at(port0, ub), pb1 = *at(port1, ub);
+        const v4i ra = *rec(agent, ua), rb = *rec(agent, ub);
+        const int la = ra.x, lb = rb.x;
+        const int pa0 = ra.y, pa1 = ra.z;
+        const int pb0 = rb.y, pb1 = rb.z;
         if constexpr (ENGINE == 1)
-          pass_interp<QCAP>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, label, port0, port1, bind,
+          pass_interp<QCAP>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, agent, bind,
                             stuck, rule_of, templ, arity, g_templ, g_arity, ns, nq_l, nq_g,
                             &s_cnt[cn], &s_status, &s_agent_top, &s_name_top, &s_nstuck, &s_loops,
                             s_rc);
         else
-          pass_uniform<QCAP, MAXL>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, label, port0, port1, bind,
+          pass_uniform<QCAP, MAXL>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, agent, bind,
                              stuck, rule_of, templ, arity, g_templ, g_arity, ns, nq_l, nq_g,
                              &s_cnt[cn], &s_status, &s_agent_top, &s_name_top, &s_nstuck, &s_loops,
                              s_rc);
@@ -1058,11 +1076,8 @@ __global__ __launch_bounds__(256) void k_jump_grid(const NetDesc *__restrict__ d
 
 // restore one net to its loaded state with the lanes tid, tid + stride, ...
 __device__ __forceinline__ void reset_net(const NetDesc &D, int nr, int tid, int stride) {
-  for (int i = tid; i < D.n_agents0; i += stride) {
-    D.label[i] = D.init_label[i];
-    D.port0[i] = D.init_port[2 * i];
-    D.port1[i] = D.init_port[2 * i + 1];
-  }
+  for (int i = tid; i < D.n_agents0; i += stride)
+    *rec((gint *)D.agent, (unsigned)i) = mkrec(D.init_label[i], D.init_port[2 * i], D.init_port[2 * i + 1]);
   gint2 *q0 = (gint2 *)D.queue0;
   for (int i = tid; i < D.n_eqs0; i += stride) q0[i] = pk(D.init_eq[2 * i], D.init_eq[2 * i + 1]);
   for (int i = tid; i < D.n_names0; i += stride) D.bind[i] = EMPTY;

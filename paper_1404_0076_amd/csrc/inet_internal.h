@@ -70,9 +70,7 @@ enum { PHASE_INIT = 0, PHASE_RUN = 1, PHASE_DONE = 2 };
 
 // per-net descriptor (read-only for the kernels)
 struct NetDesc {
-  int32_t *label;
-  int32_t *port0;
-  int32_t *port1;
+  int32_t *agent;  // [agent_cap][4]: label, port 0, port 1, unused (16-byte records)
   int32_t *bind;
   unsigned long long *queue0;  // pairs as 64-bit words, x in the low half
   unsigned long long *queue1;

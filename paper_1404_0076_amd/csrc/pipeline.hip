@@ -50,21 +50,22 @@ __device__ __forceinline__ int hi(u64 w) { return (int)(unsigned)(w >> 32); }
 // counters of one iteration, on the device
 enum { C_INT = 0, C_LOOPS = 1, C_NOMEM = 2, C_STUCK = 3, C_SELECTED = 4, C_UNIQUE = 6, C_WORDS = 8 };
 
-// the rule code of an equation between two agents, -1 if none
-__device__ __forceinline__ int rule_code(int u, int v, const int *label, const int *rule_of,
+// the rule code of an equation between two agents, -1 if none (agent records
+// are {label, port 0, port 1, unused})
+__device__ __forceinline__ int rule_code(int u, int v, const int *agent, const int *rule_of,
                                          int ns) {
   if (u < 0 || v < 0) return -1;
-  return rule_of[label[u] * ns + label[v]];
+  return rule_of[agent[4 * (size_t)u] * ns + agent[4 * (size_t)v]];
 }
 
 // what an equation allocates if it is reduced: agents in the high half,
 // names in the low half
-__global__ void k_pp_need(const u64 *__restrict__ eq, int m, const int *__restrict__ label,
+__global__ void k_pp_need(const u64 *__restrict__ eq, int m, const int *__restrict__ agent,
                           const int *__restrict__ rules, int ns, int nr, u64 *__restrict__ need) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
   const u64 e = eq[i];
-  const int code = rule_code(lo(e), hi(e), label, rules, ns);
+  const int code = rule_code(lo(e), hi(e), agent, rules, ns);
   u64 w = 0;
   if (code >= 0) {
     const int *T = rules + ns * ns + (code >> 1) * RT_WORDS;
@@ -93,14 +94,16 @@ __global__ void k_pp_int(const u64 *__restrict__ eq, int m, const u64 *__restric
   for (int j = 0; j < n_slots; j++) o[j] = DUMMY;
   const u64 e = eq[i];
   int a = lo(e), b = hi(e);
-  const int code = rule_code(a, b, D.label, rules, ns);
+  const int code = rule_code(a, b, D.agent, rules, ns);
   if (code < 0) {  // not an active pair with a rule: the equation stays
     o[0] = e;
     return;
   }
   if (code & 1) { const int t = a; a = b; b = t; }
   const int *T = rules + ns * ns + (code >> 1) * RT_WORDS;
-  const int pa0 = D.port0[a], pa1 = D.port1[a], pb0 = D.port0[b], pb1 = D.port1[b];
+  int *ag = D.agent;
+  const int pa0 = ag[4 * (size_t)a + 1], pa1 = ag[4 * (size_t)a + 2];
+  const int pb0 = ag[4 * (size_t)b + 1], pb1 = ag[4 * (size_t)b + 2];
   const u64 off = incl[i] - need[i];
   const int my_a = agent_top + hi(off), my_n = name_top + lo(off);
   const int nnew = T[RT_NNEW], nalloc = T[RT_NALLOC], nfresh = T[RT_NFRESH], neq = T[RT_NEQ];
@@ -110,9 +113,9 @@ __global__ void k_pp_int(const u64 *__restrict__ eq, int m, const u64 *__restric
   }
   for (int k = 0; k < nnew; k++) {
     const int slot = k == 0 ? a : (k == 1 ? b : my_a + k - 2);
-    D.label[slot] = T[RT_LABEL + k];
-    D.port0[slot] = operand(T[RT_PORT + 2 * k], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
-    D.port1[slot] = operand(T[RT_PORT + 2 * k + 1], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
+    ag[4 * (size_t)slot] = T[RT_LABEL + k];
+    ag[4 * (size_t)slot + 1] = operand(T[RT_PORT + 2 * k], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
+    ag[4 * (size_t)slot + 2] = operand(T[RT_PORT + 2 * k + 1], a, b, pa0, pa1, pb0, pb1, my_a, my_n);
   }
   for (int f = 0; f < nfresh; f++) D.bind[my_n + f] = EMPTY;
   int k = 0;
@@ -236,7 +239,7 @@ int pipeline_net(inet_net *h, int i, hipStream_t s, uint64_t max_iter, Buffers &
     int n_int = 0;
     if (m) {
       // int: allocation by prefix sum, then n slots per equation
-      hipLaunchKernelGGL(k_pp_need, dim3(grid_of(m)), dim3(256), 0, s, B.eq, m, D.label,
+      hipLaunchKernelGGL(k_pp_need, dim3(grid_of(m)), dim3(256), 0, s, B.eq, m, D.agent,
                          h->d_rules, ns, R.nr, B.need);
       size_t sb = B.scratch_bytes;
       HIPCHK(rocprim::inclusive_scan(B.scratch, sb, B.need, B.incl, (size_t)m,

@@ -121,12 +121,15 @@ int canonical_stream(const CompiledRules &R, const int32_t *label, const int32_t
 int readback_net(const CompiledRules &R, const NetDesc &D, const NetState &s,
                  const std::vector<int32_t> &iface, std::vector<int32_t> *out) {
   const int64_t na = s.agent_top, nc = s.name_top;
-  std::vector<int32_t> label(na), p0(na), p1(na), bind(nc);
+  std::vector<int32_t> rec(4 * (size_t)na), label(na), p0(na), p1(na), bind(nc);
   std::vector<int2> stuck(s.n_stuck);
   if (na) {
-    HIPCHK(hipMemcpy(label.data(), D.label, 4 * na, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(p0.data(), D.port0, 4 * na, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(p1.data(), D.port1, 4 * na, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(rec.data(), D.agent, 16 * (size_t)na, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < na; i++) {
+      label[i] = rec[4 * i];
+      p0[i] = rec[4 * i + 1];
+      p1[i] = rec[4 * i + 2];
+    }
   }
   if (nc) HIPCHK(hipMemcpy(bind.data(), D.bind, 4 * nc, hipMemcpyDeviceToHost));
   if (s.n_stuck)

@@ -29,12 +29,12 @@ bool plan_net(int64_t n_agents, int64_t n_eqs, int64_t n_names, int64_t agent_ca
   // exceeds agent_cap / 2; the initial equations may be more numerous
   const int64_t qcap = std::max<int64_t>(n_eqs, agent_cap / 2 + 2);
   const int64_t scap = agent_cap / 2 + 2;
-  if (agent_cap > kMaxCap || name_cap > kMaxCap || qcap > kMaxCap) return false;
+  if (agent_cap > kMaxAgentCap || name_cap > kMaxCap || qcap > kMaxCap) return false;
   p->agent_cap = agent_cap;
   p->name_cap = name_cap;
   p->qcap = qcap;
   p->scap = scap;
-  p->bytes = 3 * al(4 * (size_t)agent_cap) + al(4 * (size_t)name_cap) + 2 * al(8 * (size_t)qcap) +
+  p->bytes = al(16 * (size_t)agent_cap) + al(4 * (size_t)name_cap) + 2 * al(8 * (size_t)qcap) +
              al(8 * (size_t)scap);
   return true;
 }
@@ -52,7 +52,7 @@ size_t global_bytes(const CompiledRules &R, int32_t n_nets, int64_t total_agents
 int validate_net(const CompiledRules &R, const int32_t *label, const int32_t *port, int64_t na,
                  const int32_t *eql, const int32_t *eqr, int64_t ne, int32_t nn,
                  std::vector<int32_t> *iface) {
-  if (na < 0 || ne < 0 || nn < 0 || na > kMaxCap || nn > kMaxCap) return INET_EINVAL;
+  if (na < 0 || ne < 0 || nn < 0 || na > kMaxAgentCap || nn > kMaxCap) return INET_EINVAL;
   std::vector<int32_t> refs((size_t)na, 0);
   std::vector<int32_t> ncnt((size_t)nn, 0);
   auto use = [&](int32_t v) -> bool {
@@ -235,9 +235,7 @@ int inet_batch_load(const inet_rules *rules, int32_t n_nets, const int32_t *labe
   for (int32_t i = 0; i < n_nets; i++) {
     const NetPlan &P = plans[i];
     NetDesc &D = h->descs[i];
-    D.label = (int32_t *)take(4 * (size_t)P.agent_cap);
-    D.port0 = (int32_t *)take(4 * (size_t)P.agent_cap);
-    D.port1 = (int32_t *)take(4 * (size_t)P.agent_cap);
+    D.agent = (int32_t *)take(16 * (size_t)P.agent_cap);
     D.bind = (int32_t *)take(4 * (size_t)P.name_cap);
     D.queue0 = (unsigned long long *)take(8 * (size_t)P.qcap);
     D.queue1 = (unsigned long long *)take(8 * (size_t)P.qcap);

@@ -53,6 +53,7 @@ LaunchShape shape_for(int wg, int engine, int maxl);
 
 constexpr uint32_t kStepsPerLaunch = 1u << 24;  // bound on one launch of an unbounded reduce
 constexpr int64_t kMaxCap = (int64_t(1) << 29) - 16;  // byte offsets of 8-byte entries fit 32 bits
+constexpr int64_t kMaxAgentCap = (int64_t(1) << 28) - 16;  // and those of 16-byte agent records
 
 struct NetPlan {
   int64_t agent_cap, name_cap, qcap, scap;

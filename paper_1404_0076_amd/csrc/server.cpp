@@ -199,9 +199,7 @@ int inet_server_submit(inet_server *s, const int32_t *label, const int32_t *port
   char *p = s->dev + off;
   auto take = [&](size_t bytes) { char *q = p; p += al(bytes); return q; };
   NetDesc &D = S.desc;
-  D.label = (int32_t *)take(4 * (size_t)P.agent_cap);
-  D.port0 = (int32_t *)take(4 * (size_t)P.agent_cap);
-  D.port1 = (int32_t *)take(4 * (size_t)P.agent_cap);
+  D.agent = (int32_t *)take(16 * (size_t)P.agent_cap);
   D.bind = (int32_t *)take(4 * (size_t)P.name_cap);
   D.queue0 = (unsigned long long *)take(8 * (size_t)P.qcap);
   D.queue1 = (unsigned long long *)take(8 * (size_t)P.qcap);
@@ -466,9 +464,7 @@ int inet_server_run(inet_server *s, int32_t n_pool, const int32_t *label, const 
     char *q = s->dev + off;
     auto tk = [&](size_t bytes) { char *r = q; q += al(bytes); return r; };
     NetDesc &D = S.desc;
-    D.label = (int32_t *)tk(4 * (size_t)P.agent_cap);
-    D.port0 = (int32_t *)tk(4 * (size_t)P.agent_cap);
-    D.port1 = (int32_t *)tk(4 * (size_t)P.agent_cap);
+    D.agent = (int32_t *)tk(16 * (size_t)P.agent_cap);
     D.bind = (int32_t *)tk(4 * (size_t)P.name_cap);
     D.queue0 = (unsigned long long *)tk(8 * (size_t)P.qcap);
     D.queue1 = (unsigned long long *)tk(8 * (size_t)P.qcap);

@@ -80,3 +80,16 @@ def test_algae_27_full():
     assert tuple(int(c) for c in pr) == algae_per_rule(27)
     assert decode_letters(nf, CAT, {LA: "a", LB: "b"}) == algae_string(27)
     assert_same(g, oracle_run(ALGAE, net), "algae 27")
+
+
+@pytest.mark.parametrize("engine", [0, 2])
+def test_wide_frontier_single_wave(engine):
+    # a one-wave engine (64 lanes) whose frontier far outgrows its LDS tile
+    # (512 pairs): the overflow goes through the net's global queue
+    for rules, net in ((ALGAE, nets.algae_net(18)),
+                       (nets.arith_rules(), nets.config1_add_tree(1, 2048, 8))):
+        ref = oracle_run(rules, net)
+        say("wide", net.meta.get("family"), "engine", engine)
+        res, nf, pr = g = P.reduce_net(rules, net, wg_size=64, engine=engine)
+        assert res.max_frontier > 512
+        assert_same(g, ref, f"{net.meta.get('family')} wg 64")
