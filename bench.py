@@ -297,7 +297,9 @@ def main():
         net_list = [nets.config1_add_tree(args.seed)]
         workload = {"workload": f"single net: balanced Add tree over 1024 numerals in [0,256), "
                                 f"seed {args.seed}"}
-    wg = args.wg or (64 if len(net_list) > 1 else 1024)
+    # 1024-lane engines: all waves step together while a frontier is wide,
+    # wave 0 alone (no barriers) while it is narrow
+    wg = args.wg or 1024
     if args.max_resident < 0:
         # batch: one engine per compute unit (the longest net's engine then has
         # its CU to itself; the other engines still finish the rest within its

@@ -809,6 +809,8 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
   __shared__ int s_cnt[3];
   __shared__ int s_net;
   __shared__ int s_agent_top, s_name_top, s_status, s_nstuck, s_loops, s_maxf;
+  __shared__ unsigned s_steps;  // hand-over from one-wave steps (engine 3)
+  __shared__ int s_cur;
   __shared__ unsigned long long s_rc[MAXRULES];
 
   const int tid = threadIdx.x;
@@ -876,11 +878,13 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
 
 #ifdef INET_STATIC_RULES
     if constexpr (ENGINE == 3) {
-      constexpr bool SOLO = WG == 64;
-      if constexpr (SOLO) {
-        // one wave: the counters live in registers; the wave's own memory
-        // operations are performed in order, so no barrier separates steps
-        __syncthreads();
+      unsigned rc_lane = 0;  // lane r of each wave: interactions of rule r in this launch
+      // Steps of wave 0 alone, while the frontier holds at most `limit` pairs:
+      // the counters live in registers and no barrier separates steps (a
+      // wave's own memory operations are performed in order).  The other waves
+      // of a wider engine wait at the caller's barrier meanwhile.  On return
+      // the state is back in LDS, with the frontier count in s_cnt[ci].
+      auto solo = [&](int limit) {
         Ctr<true> C;
         C.agent_top = __builtin_amdgcn_readfirstlane(s_agent_top);
         C.name_top = __builtin_amdgcn_readfirstlane(s_name_top);
@@ -889,22 +893,20 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
         C.next = 0;
         int n = __builtin_amdgcn_readfirstlane(s_cnt[ci]);
         int maxf = __builtin_amdgcn_readfirstlane(s_maxf);
-        unsigned rc_lane = 0;  // lane r: interactions of rule r in this launch
-        while (n > 0 && C.err >= 0 && steps < stop) {
+        while (n > 0 && n <= limit && C.err >= 0 && steps < stop) {
           if (n > maxf) maxf = n;
           const Pair *cq_l = q[cur];
           const gint2 *cq_g = cur ? queue1 : queue0;
           Pair *nq_l = q[cur ^ 1];
           gint2 *nq_g = cur ? queue0 : queue1;
           C.next = 0;
-          for (int base = 0; base < n; base += WG) {
+          for (int base = 0; base < n; base += 64) {
             bool valid;
             int a, b, la, lb, pa0, pa1, pb0, pb1;
-            fetch_pair<WG, QCAP>(base, n, tid, cq_l, cq_g, agent, valid, a, b, la, lb, pa0, pa1,
+            fetch_pair<64, QCAP>(base, n, tid, cq_l, cq_g, agent, valid, a, b, la, lb, pa0, pa1,
                                  pb0, pb1);
             pass_static<QCAP, MAXL, true>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, agent, bind,
-                                          stuck, rule_of, nq_l, nq_g, C, &s_loops,
-                                          rc_lane);
+                                          stuck, rule_of, nq_l, nq_g, C, &s_loops, rc_lane);
           }
           // lanes of one wave need no cache action or wait to see each
           // other's writes (wavefront scope); the fence only keeps the
@@ -914,28 +916,43 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
           cur ^= 1;
           n = C.next;
         }
-        if (rc_lane) atomicAdd(&s_rc[tid], (unsigned long long)rc_lane);
-        __syncthreads();
         if (tid == 0) {
           s_cnt[ci] = n;
+          s_cnt[ci == 2 ? 0 : ci + 1] = 0;
+          s_cnt[ci == 0 ? 2 : ci - 1] = 0;
           s_agent_top = C.agent_top;
           s_name_top = C.name_top;
           s_nstuck = C.nstuck;
           s_maxf = maxf;
+          s_steps = steps;
+          s_cur = cur;
           if (C.err < 0) s_status = C.err;
         }
+      };
+      if constexpr (WG == 64) {
+        __syncthreads();
+        solo(0x7fffffff);
+        if (rc_lane) atomicAdd(&s_rc[tid], (unsigned long long)rc_lane);
         __syncthreads();
       } else {
+        // a wider engine: all waves step together while the frontier is wider
+        // than one wave, wave 0 alone while it is not
         Ctr<false> C;
         C.agent_top = &s_agent_top;
         C.name_top = &s_name_top;
         C.nstuck = &s_nstuck;
         C.status = &s_status;
-        unsigned rc_lane = 0;  // lane r of each wave: interactions of rule r
         for (;;) {
           __syncthreads();
           const int n = s_cnt[ci];
           if (n == 0 || s_status < 0 || steps >= stop) break;
+          if (n <= 64) {
+            if (tid < 64) solo(64);
+            __syncthreads();
+            steps = s_steps;
+            cur = s_cur;
+            continue;
+          }
           const int cn = ci == 2 ? 0 : ci + 1;
           const int cnn = cn == 2 ? 0 : cn + 1;
           if (tid == 0) {
