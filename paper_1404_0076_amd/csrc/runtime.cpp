@@ -105,9 +105,9 @@ int validate_net(const CompiledRules &R, const int32_t *label, const int32_t *po
 
 LaunchShape effective_shape(const inet_config &cfg, int n_nets, const CompiledRules &R) {
   int wg = cfg.wg_size;
-  // one net: the widest engine (its frontier can be wide); many nets: one-wave
-  // engines, which need no barrier between steps
-  if (wg <= 0) wg = n_nets == 1 ? 1024 : 64;
+  // 1024-lane engines: for engine 3 a hybrid that steps with wave 0 alone
+  // while the frontier fits one wave and with all waves while it is wider
+  if (wg <= 0) wg = 1024;
   int engine = cfg.engine;
   if (engine == 0) {
     // the rule table compiled into the kernel when hipRTC can build it

@@ -98,13 +98,11 @@ void give_range(inet_server *s, size_t off, size_t len) {
   }
 }
 
-// a round runs every resident net for a bounded number of steps, so a wide
-// frontier must not make the round long: engines of 256 lanes unless the
-// caller chose a width
-inet_config serving_config(inet_config cfg) {
-  if (cfg.wg_size == 0) cfg.wg_size = 256;
-  return cfg;
-}
+// the engine width of a round: the library default unless the caller chose
+// one (a round runs every resident net for a bounded number of steps, so a
+// wide frontier must not lengthen it: the default engines handle wide
+// frontiers with all their waves)
+inet_config serving_config(inet_config cfg) { return cfg; }
 
 inet_server::Slot *slot_of(inet_server *s, int64_t ticket) {
   auto it = s->by_ticket.find(ticket);
