@@ -119,7 +119,11 @@ typedef struct {
 
 /* Launch shape of the reduction kernel; 0 fields take the defaults. */
 typedef struct {
-  int32_t wg_size;          /* lanes per net engine: 64,128,256,512,1024   */
+  int32_t wg_size;          /* lanes per net engine: 64,128,256,512,1024;
+                               0 takes 1024.  With engine 3 a wider engine
+                               runs its first wave alone while the active
+                               pairs fit one wave (no group barrier per
+                               step) and all its waves once they do not   */
   int32_t jump;             /* 1: compress name chains after the loop      */
   int32_t max_resident;     /* cap on simultaneously resident net engines  */
   int32_t engine;           /* 0 default (3 when the run-time compiler can
