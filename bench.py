@@ -218,7 +218,7 @@ def main():
     ap.add_argument("--algae-n", type=int, default=27)
     ap.add_argument("--rate", type=float, default=1.0e4, help="serve: Poisson arrival rate (nets/s)")
     ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals")
-    ap.add_argument("--pool", type=int, default=8192, help="serve: request pool size")
+    ap.add_argument("--pool", type=int, default=65536, help="serve: request pool size")
     ap.add_argument("--round-steps", type=int, default=256, help="serve: step budget per round")
     ap.add_argument("--serve-loop", default="native", choices=["native", "python"],
                     help="serve: the library's serving loop or the Python driver")

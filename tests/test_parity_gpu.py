@@ -263,29 +263,75 @@ def test_batch_matches_single_and_oracle():
 
 
 @pytest.mark.slow
-def test_config1_add_tree_full():
-    net = nets.config1_add_tree(0)
-    say("config1", net.n_agents)
+@pytest.mark.parametrize("seed", range(5))
+def test_config1_add_tree_full(seed):
+    net = nets.config1_add_tree(seed)
+    say("config1", seed, net.n_agents)
     g = gpu(R, net, agent_cap=1 << 20, name_cap=1 << 22)
     assert g[0].interactions == tree_count(net.meta["values"])
-    assert_same(g, oracle_run(R, net), "config1")
+    assert_same(g, oracle_run(R, net), f"config1 seed {seed}")
 
 
 @pytest.mark.slow
-def test_config2_mul_full():
-    net = nets.config2_mul(0)
+@pytest.mark.parametrize("seed", range(5))
+def test_config2_mul_full(seed):
+    net = nets.config2_mul(seed)
     a, b = net.meta["a"], net.meta["b"]
-    say("config2", a, b)
+    say("config2", seed, a, b)
     g = gpu(R, net, agent_cap=a * b + 4 * (a + b) + 4096, name_cap=4 * a * b + 8 * (a + b) + 4096)
     assert g[0].interactions == mul_count(a, b)
-    assert_same(g, oracle_run(R, net), "config2")
+    assert_same(g, oracle_run(R, net), f"config2 seed {seed}")
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("n", [20, 23])
+@pytest.mark.parametrize("n", [20, 23, 25, 27])
 def test_config3_fib_full(n):
     say("config3", n)
     net = nets.fib_net(n)
     g = gpu(R, net, agent_cap=4 * fib_count(n), name_cap=8 * fib_count(n))
     assert g[0].interactions == fib_count(n)
     assert_same(g, oracle_run(R, net), f"fib {n}")
+
+
+@pytest.mark.slow
+def test_config4_batch_full():
+    """The 4096-net batch (seed 0) in the launch configuration the benchmark
+    times: 1024-lane engines, one resident engine per compute unit, longest
+    critical path first, heaps sized exactly; every net against the oracle,
+    eagerly and by HIP-graph replay."""
+    import torch
+    batch = nets.config4_batch(seed=0)
+    say("config4 oracle", len(batch))
+    refs = [oracle_run(R, net) for net in batch]
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    # sizing run: generous heaps (a rule makes at most 3 agents beyond the
+    # pair's two slots and at most 8 fresh names)
+    caps = [net.n_agents + 3 * r.interactions + 64 for net, r in zip(batch, refs)]
+    ncaps = [net.n_names + 8 * r.interactions + 64 for net, r in zip(batch, refs)]
+    say("config4 sizing run, resident", n_cu)
+    h = P.batch_load(R, batch, agent_caps=caps, name_caps=ncaps)
+    h.set_config(wg_size=1024, max_resident=n_cu)
+    rs = h.reduce()
+    used_a = np.array([r.agents_used for r in rs], np.int64)
+    used_n = np.array([r.names_used for r in rs], np.int64)
+    steps = np.array([r.steps for r in rs], np.int64)
+    for i, net in enumerate(batch):
+        assert_same((rs[i], h.readback(i), h.per_rule(i)), refs[i], f"net {i}")
+    h.free()
+    say("config4 exact heaps, longest first")
+    h = P.batch_load(R, batch, agent_caps=used_a + 64, name_caps=used_n + 64)
+    h.set_config(wg_size=1024, max_resident=n_cu)
+    h.set_order(np.argsort(-steps, kind="stable").astype(np.int32))
+    h.reset()
+    rs = h.reduce()
+    for i in range(len(batch)):
+        assert_same((rs[i], h.readback(i), h.per_rule(i)), refs[i], f"exact heaps net {i}")
+    say("config4 graph replay")
+    h.graph_capture()
+    for rep in range(2):
+        h.graph_launch()
+        torch.cuda.synchronize()
+        rs = h.results()
+        for i in range(len(batch)):
+            assert_same((rs[i], h.readback(i), h.per_rule(i)), refs[i], f"graph {rep} net {i}")
+    h.free()
