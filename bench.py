@@ -67,7 +67,7 @@ def counter_traffic(workload_key: str):
 
 def kernel_name(engine: int, wg: int) -> str:
     """Name of the reduce kernel as the profiler lists it."""
-    return f"inet_static_{wg}" if engine == 3 else "k_reduce"
+    return f"inet_static_{wg}" if engine >= 3 else "k_reduce"
 
 
 def size_batch(P, R, net_list, wg, engine=0):
@@ -230,7 +230,8 @@ def main():
                     help="cap on simultaneously resident net engines (0: as many as fit; "
                          "default: one per compute unit for a batch)")
     ap.add_argument("--engine", type=int, default=0,
-                    help="0 default, 1 interpreter, 2 rule-uniform, 3 rules compiled in at load time")
+                    help="0 default, 1 interpreter, 2 rule-uniform, 3 rules compiled in at load time, "
+                         "4 the same with per-lane atomic append")
     ap.add_argument("--autotune", action="store_true",
                     help="pick engine width and variant with the autotuner (cached)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)

@@ -131,7 +131,11 @@ typedef struct {
                                interpreter; 2 rule-uniform execution with
                                the templates read at run time; 3 the same
                                with the rule table compiled into the kernel
-                               at load time (hipRTC)                       */
+                               at load time (hipRTC); 4 engine 3 with the
+                               atomic append of Section 4.2: each lane
+                               reserves its agents, name cells and frontier
+                               entries with atomics of its own (all waves
+                               step together, at every frontier width)    */
 } inet_config;
 
 typedef struct inet_net inet_net;
@@ -216,10 +220,11 @@ int inet_rule_bytes(const inet_net *h, int32_t *bytes, int32_t cap);
 int inet_rules_check(const inet_rules *rules, int32_t *n_new, int32_t *n_fresh, int32_t *n_links,
                      int32_t *bytes, int32_t cap);
 
-/* Host only: build the engine specialised for this rule table (engine 3) for
- * the given device architecture (e.g. "gfx950") with the run-time compiler,
- * without a device; *code_bytes gets the code object size, log (may be NULL)
- * the compiler's messages.  INET_ENOSYS if the compiler fails. */
+/* Host only: build the engines specialised for this rule table (engines 3
+ * and 4) for the given device architecture (e.g. "gfx950") with the run-time
+ * compiler, without a device; *code_bytes gets the total size of the two code
+ * objects, log (may be NULL) the compiler's messages.  INET_ENOSYS if the
+ * compiler fails. */
 int inet_jit_build(const inet_rules *rules, const char *arch, size_t *code_bytes, char *log,
                    size_t log_cap);
 

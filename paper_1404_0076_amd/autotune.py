@@ -20,7 +20,8 @@ from . import batch_load
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 WIDTHS = (64, 128, 256, 512, 1024)
-ENGINES = (2, 3)  # rule-uniform, and the rule table compiled in (engine 1 is never faster)
+ENGINES = (2, 3, 4)  # rule-uniform, rules compiled in, and that with atomic append
+# (engine 1 is never faster)
 RESIDENTS = (0, 256)  # as many engines as fit, or one per compute unit
 
 

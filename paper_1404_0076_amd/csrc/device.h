@@ -655,7 +655,11 @@ __device__ __forceinline__ void decide_links(const Lane &L, gint *bind, unsigned
   }
 }
 
-template <int QCAP, int MAXL, bool SOLO>
+// LANE: the atomic-append variant (the proposal of Section 4.2 to drop the
+// merge of result arrays): every lane reserves its own agents, cells and
+// frontier entries with one atomic each, instead of one reservation per rule
+// group of a wave ranked by mask counts
+template <int QCAP, int MAXL, bool SOLO, bool LANE>
 __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, int lb, int pa0,
                                             int pa1, int pb0, int pb1, const NetDesc &D,
                                             gint *agent, gint *bind,
@@ -706,34 +710,61 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
   for_rules<0>(rid, ballot(rid >= 0), [&](auto ic, unsigned long long gm) {
       constexpr int R = decltype(ic)::value;
       constexpr int nalloc = rt::T[R][RT_NALLOC], nfresh = rt::T[R][RT_NFRESH];
-      const int lead = __builtin_ctzll(gm);
       const bool mine = rid == R;
       const int cnt = __popcll(gm);
-      int ba = 0, bn = 0;
-      if constexpr (nalloc > 0) ba = C.agents(nalloc * cnt, lane, lead);
-      if constexpr (nfresh > 0) bn = C.names(nfresh * cnt, lane, lead);
-      // interactions per rule: lane R of the wave counts rule R (the lane id
-      // is opaque so that the test is not hoisted, per rule, out of the loop)
-      rc_lane += opaque(lane) == R ? (unsigned)cnt : 0u;
-      if ((nalloc > 0 && ba + nalloc * cnt > D.agent_cap) ||
-          (nfresh > 0 && bn + nfresh * cnt > D.name_cap)) {
-        // out of heap: the step ends with ENOMEM; these lanes issue nothing,
-        // and their exchange results are never read
-        C.fail_uniform(lane, lead);
-        if (mine) rid = -1;
-        return;
-      }
-      if (mine) {
-        const int rank = count_below(gm);
-        Lane X = opaque(L);
-        X.my_a = ba + nalloc * rank;
-        X.my_n = bn + nfresh * rank;
-        L.my_a = X.my_a;
-        L.my_n = X.my_n;
-        st_agents<R, 0>(X, agent);
+      if constexpr (LANE) {
+        rc_lane += opaque(lane) == R ? (unsigned)cnt : 0u;
+        if (mine) {
+          int ma = 0, mn = 0;
+          if constexpr (nalloc > 0) ma = atomicAdd(C.agent_top, nalloc);
+          if constexpr (nfresh > 0) mn = atomicAdd(C.name_top, nfresh);
+          if ((nalloc > 0 && ma + nalloc > D.agent_cap) ||
+              (nfresh > 0 && mn + nfresh > D.name_cap)) {
+            *C.status = ST_ENOMEM;  // the step ends with ENOMEM; this lane issues nothing
+            rid = -1;
+          } else {
+            Lane X = opaque(L);
+            X.my_a = ma;
+            X.my_n = mn;
+            L.my_a = X.my_a;
+            L.my_n = X.my_n;
+            issue_links<R, 0, MAXL>(X, bind, eo[R]);
+            st_agents<R, 0>(X, agent);
 #pragma unroll
-        for (int f = 0; f < nfresh; f++) *at(bind, (unsigned)(X.my_n + f)) = EMPTY;
-        issue_links<R, 0, MAXL>(X, bind, eo[R]);
+            for (int f = 0; f < nfresh; f++) *at(bind, (unsigned)(X.my_n + f)) = EMPTY;
+          }
+        }
+      } else {
+        const int lead = __builtin_ctzll(gm);
+        int ba = 0, bn = 0;
+        if constexpr (nalloc > 0) ba = C.agents(nalloc * cnt, lane, lead);
+        if constexpr (nfresh > 0) bn = C.names(nfresh * cnt, lane, lead);
+        // interactions per rule: lane R of the wave counts rule R (the lane id
+        // is opaque so that the test is not hoisted, per rule, out of the loop)
+        rc_lane += opaque(lane) == R ? (unsigned)cnt : 0u;
+        if ((nalloc > 0 && ba + nalloc * cnt > D.agent_cap) ||
+            (nfresh > 0 && bn + nfresh * cnt > D.name_cap)) {
+          // out of heap: the step ends with ENOMEM; these lanes issue nothing,
+          // and their exchange results are never read
+          C.fail_uniform(lane, lead);
+          if (mine) rid = -1;
+          return;
+        }
+        if (mine) {
+          const int rank = count_below(gm);
+          Lane X = opaque(L);
+          X.my_a = ba + nalloc * rank;
+          X.my_n = bn + nfresh * rank;
+          L.my_a = X.my_a;
+          L.my_n = X.my_n;
+          // the exchanges first, so that they are in flight while the new
+          // agents and cells are written (a lane reads agent records only at
+          // the next step, and no link of this step names a fresh cell)
+          issue_links<R, 0, MAXL>(X, bind, eo[R]);
+          st_agents<R, 0>(X, agent);
+#pragma unroll
+          for (int f = 0; f < nfresh; f++) *at(bind, (unsigned)(X.my_n + f)) = EMPTY;
+        }
       }
   });
   // second walk: decide every link
@@ -745,11 +776,22 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
       decide_links<R, 0, MAXL>(opaque(L), bind, (unsigned)D.name_cap, eo[R], pu, pv, loops, bad);
   });
   // append the wave's new active pairs
+  if constexpr (LANE) {
+#pragma unroll
+    for (int j = 0; j < MAXL; j++) {
+      if (pu[j] >= 0) {
+        const int i = atomicAdd(C.next, 1);
+        if (i < QCAP) nq_l[i] = mkpair(pu[j], pv[j]);
+        else if (i < D.qcap) *at2(nq_g, (unsigned)i) = pk(pu[j], pv[j]);
+        else lane_err = true;
+      }
+    }
+  }
   unsigned long long m[MAXL];
   int tot = 0;
 #pragma unroll
   for (int j = 0; j < MAXL; j++) {
-    m[j] = ballot(pu[j] >= 0);
+    m[j] = LANE ? 0ull : ballot(pu[j] >= 0);
     tot += __popcll(m[j]);
   }
   if (tot) {
@@ -877,7 +919,10 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
     }
 
 #ifdef INET_STATIC_RULES
-    if constexpr (ENGINE == 3) {
+    if constexpr (ENGINE == 3 || ENGINE == 4) {
+      // engine 4 reserves heap and frontier space per lane (atomic append);
+      // its counters are shared words, so it always steps as a group
+      constexpr bool LANE = ENGINE == 4;
       unsigned rc_lane = 0;  // lane r of each wave: interactions of rule r in this launch
       // Steps of wave 0 alone, while the frontier holds at most `limit` pairs:
       // the counters live in registers and no barrier separates steps (a
@@ -905,7 +950,7 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
             int a, b, la, lb, pa0, pa1, pb0, pb1;
             fetch_pair<64, QCAP>(base, n, tid, cq_l, cq_g, agent, valid, a, b, la, lb, pa0, pa1,
                                  pb0, pb1);
-            pass_static<QCAP, MAXL, true>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, agent, bind,
+            pass_static<QCAP, MAXL, true, false>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, agent, bind,
                                           stuck, rule_of, nq_l, nq_g, C, &s_loops, rc_lane);
           }
           // lanes of one wave need no cache action or wait to see each
@@ -929,7 +974,7 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
           if (C.err < 0) s_status = C.err;
         }
       };
-      if constexpr (WG == 64) {
+      if constexpr (WG == 64 && !LANE) {
         __syncthreads();
         solo(0x7fffffff);
         if (rc_lane) atomicAdd(&s_rc[tid], (unsigned long long)rc_lane);
@@ -946,7 +991,7 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
           __syncthreads();
           const int n = s_cnt[ci];
           if (n == 0 || s_status < 0 || steps >= stop) break;
-          if (n <= 64) {
+          if (!LANE && n <= 64) {
             if (tid < 64) solo(64);
             __syncthreads();
             steps = s_steps;
@@ -969,7 +1014,7 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
             int a, b, la, lb, pa0, pa1, pb0, pb1;
             fetch_pair<WG, QCAP>(base, n, tid, cq_l, cq_g, agent, valid, a, b, la, lb, pa0, pa1,
                                  pb0, pb1);
-            pass_static<QCAP, MAXL, false>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, agent,
+            pass_static<QCAP, MAXL, false, LANE>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, agent,
                                            bind, stuck, rule_of, nq_l, nq_g, C,
                                            &s_loops, rc_lane);
           }

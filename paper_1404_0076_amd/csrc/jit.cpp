@@ -2,9 +2,10 @@
 //
 // The device code (device.h) is compiled with hipRTC after the compiled rule
 // templates have been written into it as constant arrays (namespace rt), so
-// each rule's right-hand side becomes straight-line code (engine 3).  One code
-// object per (rule table, device architecture) holds the kernel for every
-// engine width; it is built on first use and kept for the process.
+// each rule's right-hand side becomes straight-line code (engine 3; engine 4
+// is the same code with per-lane atomic reservations).  One code object per
+// (rule table, device architecture, engine) holds the kernel for every engine
+// width; it is built on first use and kept for the process.
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
@@ -40,7 +41,7 @@ std::map<std::string, Module> g_mods;
 
 const int kWidths[] = {64, 128, 256, 512, 1024};
 
-std::string source_for(const CompiledRules &R) {
+std::string source_for(const CompiledRules &R, int engine) {
   std::ostringstream o;
   o << "#define INET_STATIC_RULES 1\n#include \"inet_internal.h\"\n";
   o << "namespace inet { namespace rt {\n";
@@ -60,11 +61,11 @@ std::string source_for(const CompiledRules &R) {
   o << "};\n} }\n#include \"device.h\"\n";
   const int maxl = R.max_links <= 4 ? 4 : MAXEQ;
   for (int wg : kWidths) {
-    const LaunchShape sh = shape_for(wg, 3, R.max_links);
+    const LaunchShape sh = shape_for(wg, engine, R.max_links);
     o << "extern \"C\" __global__ __launch_bounds__(" << wg << ") void inet_static_" << wg
       << "(const inet::NetDesc *__restrict__ d, const int *__restrict__ ord, int n, int *ctr,"
          " const int *__restrict__ r, int ns, int nr, unsigned ms, int flags) {\n"
-      << "  inet::reduce_body<" << wg << ", " << sh.qcap << ", 3, " << maxl
+      << "  inet::reduce_body<" << wg << ", " << sh.qcap << ", " << engine << ", " << maxl
       << ">(d, ord, n, ctr, r, ns, nr, ms, flags);\n}\n";
   }
   return o.str();
@@ -85,9 +86,9 @@ std::string key_for(const CompiledRules &R, const std::string &arch) {
 }
 
 // compile the specialised engine; code object into *code (no device needed)
-int compile_code(const CompiledRules &R, const std::string &arch, std::vector<char> *code,
-                 std::string *log_out) {
-  const std::string src = source_for(R);
+int compile_code(const CompiledRules &R, const std::string &arch, int engine,
+                 std::vector<char> *code, std::string *log_out) {
+  const std::string src = source_for(R, engine);
   if (const char *dump = std::getenv("INET_JIT_DUMP")) {  // inspection aid
     if (FILE *f = std::fopen(dump, "w")) {
       std::fputs(src.c_str(), f);
@@ -124,9 +125,9 @@ int compile_code(const CompiledRules &R, const std::string &arch, std::vector<ch
   return INET_OK;
 }
 
-int build_module(const CompiledRules &R, const std::string &arch, Module *M) {
+int build_module(const CompiledRules &R, const std::string &arch, int engine, Module *M) {
   std::vector<char> code;
-  int rc = compile_code(R, arch, &code, &M->log);
+  int rc = compile_code(R, arch, engine, &code, &M->log);
   if (rc) return rc;
   if (hipModuleLoadData(&M->mod, code.data()) != hipSuccess) return INET_EHIP;
   for (int wg : kWidths) {
@@ -140,19 +141,22 @@ int build_module(const CompiledRules &R, const std::string &arch, Module *M) {
 
 }  // namespace
 
-// Kernel of engine 3 for the rule table and engine width (built on first use).
-int jit_function(const CompiledRules &R, int wg, hipFunction_t *out) {
+// Kernel of engine 3 or 4 for the rule table and engine width (built on first
+// use).
+int jit_function(const CompiledRules &R, int wg, int engine, hipFunction_t *out) {
+  if (engine != 3 && engine != 4) return INET_EINVAL;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return INET_EHIP;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return INET_EHIP;
   std::string arch(prop.gcnArchName);
-  const std::string key = key_for(R, arch) + "/" + std::to_string(dev);
+  const std::string key =
+      key_for(R, arch) + "/" + std::to_string(dev) + "/" + std::to_string(engine);
   std::lock_guard<std::mutex> lock(g_mu);
   Module &M = g_mods[key];
   if (M.failed) return INET_ENOSYS;
   if (!M.mod) {
-    int rc = build_module(R, arch, &M);
+    int rc = build_module(R, arch, engine, &M);
     if (rc) {
       M.failed = true;
       if (std::getenv("INET_JIT_LOG")) std::fprintf(stderr, "inet jit: %d\n%s\n", rc, M.log.c_str());
@@ -169,7 +173,7 @@ int jit_launch(const CompiledRules &R, const LaunchShape &sh, int grid, const Ne
                const int32_t *ord, int n, int32_t *ctr, const int32_t *r, uint32_t ms, int flags,
                hipStream_t s) {
   hipFunction_t f = nullptr;
-  int rc = jit_function(R, sh.wg, &f);
+  int rc = jit_function(R, sh.wg, sh.engine, &f);
   if (rc) return rc;
   int ns = R.ns, nr = R.nr;
   void *args[] = {(void *)&d, (void *)&ord, (void *)&n, (void *)&ctr, (void *)&r,
@@ -182,7 +186,7 @@ int jit_launch(const CompiledRules &R, const LaunchShape &sh, int grid, const Ne
 
 int jit_occupancy(const CompiledRules &R, const LaunchShape &sh, int *per_cu) {
   hipFunction_t f = nullptr;
-  int rc = jit_function(R, sh.wg, &f);
+  int rc = jit_function(R, sh.wg, sh.engine, &f);
   if (rc) return rc;
   const size_t dyn = (size_t)(R.ns * R.ns + R.nr * RT_WORDS + R.ns) * 4;
   return hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, f, sh.wg, dyn) == hipSuccess
@@ -198,13 +202,18 @@ extern "C" int inet_jit_build(const inet_rules *rules, const char *arch, size_t 
   int rc = inet::compile_rules(rules, &R);
   if (rc) return rc;
   if (!arch) return INET_EINVAL;
-  std::vector<char> code;
+  // both specialised engines (3, then 4); the first failure ends the build
+  size_t total = 0;
   std::string msg;
-  rc = inet::compile_code(R, arch, &code, &msg);
+  for (int engine = 3; engine <= 4 && rc == INET_OK; engine++) {
+    std::vector<char> code;
+    rc = inet::compile_code(R, arch, engine, &code, &msg);
+    total += code.size();
+  }
   if (log && log_cap) {
     std::strncpy(log, msg.c_str(), log_cap - 1);
     log[log_cap - 1] = 0;
   }
-  if (code_bytes) *code_bytes = code.size();
+  if (code_bytes) *code_bytes = total;
   return rc;
 }

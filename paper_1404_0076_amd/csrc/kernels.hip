@@ -52,7 +52,7 @@ bool shape_supported(int wg) {
 }
 
 LaunchShape shape_for(int wg, int engine, int maxl) {
-  const int e = (engine == 1 || engine == 3) ? engine : 2;
+  const int e = (engine == 1 || engine == 3 || engine == 4) ? engine : 2;
   switch (wg) {
     case 64: return {64, 512, e, maxl};
     case 128: return {128, 1024, e, maxl};
@@ -67,7 +67,7 @@ LaunchShape shape_for(int wg, int engine, int maxl) {
 int launch_reduce(const CompiledRules &R, const LaunchShape &sh, int grid, const NetDesc *d,
                   const int32_t *ord, int n, int32_t *ctr, const int32_t *r, uint32_t ms, int flags,
                   hipStream_t s) {
-  if (sh.engine == 3) return jit_launch(R, sh, grid, d, ord, n, ctr, r, ms, flags, s);
+  if (sh.engine >= 3) return jit_launch(R, sh, grid, d, ord, n, ctr, r, ms, flags, s);
   const int ns = R.ns, nr = R.nr;
 #define X(W, Q) \
   if (sh.wg == W && sh.qcap == Q)    \
@@ -82,7 +82,7 @@ int max_resident(const CompiledRules &R, const LaunchShape &sh, int *per_cu, int
   if (hipGetDevice(&dev) != hipSuccess) return INET_EHIP;
   if (hipDeviceGetAttribute(n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return INET_EHIP;
-  if (sh.engine == 3) return jit_occupancy(R, sh, per_cu);
+  if (sh.engine >= 3) return jit_occupancy(R, sh, per_cu);
   const int ns = R.ns, nr = R.nr;
 #define X(W, Q) \
   if (sh.wg == W && sh.qcap == Q) return occ_t<W, Q>(sh.engine, sh.maxl, ns, nr, per_cu);

@@ -112,7 +112,7 @@ LaunchShape effective_shape(const inet_config &cfg, int n_nets, const CompiledRu
   if (engine == 0) {
     // the rule table compiled into the kernel when hipRTC can build it
     hipFunction_t f = nullptr;
-    engine = jit_function(R, wg, &f) == INET_OK ? 3 : 2;
+    engine = jit_function(R, wg, 3, &f) == INET_OK ? 3 : 2;
   }
   return shape_for(wg, engine, R.max_links);
 }
@@ -295,7 +295,7 @@ int inet_load(const inet_rules *rules, const int32_t *label, const int32_t *port
 int inet_set_config(inet_net *h, const inet_config *cfg) {
   if (!h || !cfg) return INET_EINVAL;
   if (cfg->wg_size != 0 && !shape_supported(cfg->wg_size)) return INET_EINVAL;
-  if (cfg->max_resident < 0 || cfg->engine < 0 || cfg->engine > 3) return INET_EINVAL;
+  if (cfg->max_resident < 0 || cfg->engine < 0 || cfg->engine > 4) return INET_EINVAL;
   h->cfg = *cfg;
   return INET_OK;
 }

@@ -30,7 +30,8 @@ struct LaunchShape {
   int wg;
   int qcap;    // LDS frontier capacity per buffer
   int engine;  // 1: per-lane template interpreter, 2: rule-uniform execution,
-               // 3: rule-uniform with the rule table compiled in (load time)
+               // 3: rule-uniform with the rule table compiled in (load time),
+               // 4: engine 3 with per-lane atomic reservations (atomic append)
   int maxl;    // largest number of link equations of any rule
 };
 int launch_reset(const NetDesc *d_descs, const int32_t *d_idx, int n, int nr, hipStream_t s);
@@ -41,8 +42,8 @@ int launch_reduce(const CompiledRules &R, const LaunchShape &shape, int grid,
                   const int32_t *d_rules, uint32_t max_steps, int flags, hipStream_t s);
 int launch_jump_grid(const NetDesc *d_desc, int grid, hipStream_t s);
 int max_resident(const CompiledRules &R, const LaunchShape &shape, int *per_cu, int *n_cu);
-// engine 3: the rule table compiled into the kernel at load time (jit.cpp)
-int jit_function(const CompiledRules &R, int wg, hipFunction_t *out);
+// engines 3 and 4: the rule table compiled into the kernel at load time (jit.cpp)
+int jit_function(const CompiledRules &R, int wg, int engine, hipFunction_t *out);
 int jit_launch(const CompiledRules &R, const LaunchShape &sh, int grid, const NetDesc *d,
                const int32_t *ord, int n, int32_t *ctr, const int32_t *r, uint32_t ms, int flags,
                hipStream_t s);

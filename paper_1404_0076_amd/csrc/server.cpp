@@ -159,7 +159,7 @@ int inet_server_create(const inet_rules *rules, int32_t max_slots, void *dev, si
 int inet_server_set_config(inet_server *s, const inet_config *cfg) {
   if (!s || !cfg) return INET_EINVAL;
   if (cfg->wg_size != 0 && !shape_supported(cfg->wg_size)) return INET_EINVAL;
-  if (cfg->max_resident < 0 || cfg->engine < 0 || cfg->engine > 3) return INET_EINVAL;
+  if (cfg->max_resident < 0 || cfg->engine < 0 || cfg->engine > 4) return INET_EINVAL;
   s->cfg = *cfg;
   return INET_OK;
 }

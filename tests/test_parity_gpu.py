@@ -140,18 +140,19 @@ OTHER_TABLES = [
 ]
 
 
-@pytest.mark.parametrize("engine", [1, 2, 3])
+@pytest.mark.parametrize("engine", [1, 2, 3, 4])
 @pytest.mark.parametrize("wg", [64, 1024])
 def test_engines_agree(engine, wg):
     # every engine (per-lane interpreter, rule-uniform, rules compiled in at
-    # load time) gives the oracle's normal form, count and histogram
+    # load time, and that with per-lane atomic reservations) gives the
+    # oracle's normal form, count and histogram
     for net in (nets.mul_net(30, 41), nets.fib_net(12), nets.config1_add_tree(3, 64, 30), MID,
                 nets.parse_net(nets.ARITH_SIG, "<r, q | S(r) = Z, Add(q, y) = Fib(y)>")):
         say("engine", engine, wg, net.meta.get("family"))
         assert_same(gpu(R, net, wg=wg, engine=engine), oracle_run(R, net), f"engine {engine}")
 
 
-@pytest.mark.parametrize("engine", [1, 2, 3])
+@pytest.mark.parametrize("engine", [1, 2, 3, 4])
 @pytest.mark.parametrize("name,sig,texts,cases", OTHER_TABLES, ids=[t[0] for t in OTHER_TABLES])
 def test_other_rule_tables(engine, name, sig, texts, cases):
     rules = nets.parse_rules(sig, texts)
@@ -164,7 +165,7 @@ def test_other_rule_tables(engine, name, sig, texts, cases):
         assert oracle_run(rules, wide_net(7)).interactions == 3 * 7 - 1
 
 
-@pytest.mark.parametrize("engine", [1, 2, 3])
+@pytest.mark.parametrize("engine", [1, 2, 3, 4])
 def test_batch_engines_agree(engine):
     batch = [n for _, n in small_exprs(12, 12, 5, 200_000)] + \
             [nets.mul_net(5, 7), nets.fib_net(9), nets.config1_add_tree(2, 16, 12),
@@ -190,11 +191,12 @@ def test_launch_shapes_agree(wg):
         assert_same(gpu(R, net, wg=wg), oracle_run(R, net), f"wg {wg}")
 
 
-def test_steps_equal_oracle_rounds():
+@pytest.mark.parametrize("engine", [0, 4])
+def test_steps_equal_oracle_rounds(engine):
     # one GPU step reduces every active pair present after com has run to
     # closure: exactly the oracle's maximal parallel rounds
     for net in (nets.fib_net(10), nets.mul_net(12, 9), nets.config1_add_tree(1, 32, 20)):
-        res, _, _ = gpu(R, net)
+        res, _, _ = gpu(R, net, engine=engine)
         ref = oracle.reduce(R, net, schedule="rounds")
         say("rounds", res.steps, ref.rounds)
         assert res.steps == ref.rounds
@@ -225,9 +227,11 @@ def test_resume_after_step_limit():
     h.free()
 
 
-def test_out_of_memory_reported():
+@pytest.mark.parametrize("engine", [0, 4])
+def test_out_of_memory_reported(engine):
     net = nets.mul_net(30, 30)
     h = P.load(R, net, agent_cap=net.n_agents + 8, name_cap=net.n_names + 8)
+    h.set_config(engine=engine)
     res = h.reduce()[0]
     assert res.status == P.ENOMEM
     h.free()

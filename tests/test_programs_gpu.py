@@ -26,7 +26,7 @@ def say(*a):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("engine", [0, 1, 2])
+@pytest.mark.parametrize("engine", [0, 1, 2, 4])
 def test_ackermann(engine):
     for m, n in [(0, 0), (1, 3), (2, 3), (3, 0), (3, 3), (3, 5)]:
         net = nets.ackermann_net(m, n)
@@ -36,7 +36,7 @@ def test_ackermann(engine):
                         f"A({m},{n}) wg {wg}")
 
 
-@pytest.mark.parametrize("engine", [0, 1, 2])
+@pytest.mark.parametrize("engine", [0, 1, 2, 4])
 def test_algae(engine):
     for n in (0, 1, 2, 5, 10, 14):
         net = nets.algae_net(n)
@@ -82,7 +82,7 @@ def test_algae_27_full():
     assert_same(g, oracle_run(ALGAE, net), "algae 27")
 
 
-@pytest.mark.parametrize("engine", [0, 2])
+@pytest.mark.parametrize("engine", [0, 2, 4])
 def test_wide_frontier_single_wave(engine):
     # a one-wave engine (64 lanes) whose frontier far outgrows its LDS tile
     # (512 pairs): the overflow goes through the net's global queue
