@@ -581,7 +581,10 @@ __device__ __forceinline__ void link_sides(const Lane &L, int &u, int &v) {
     u = opnd<OU>(L);
     v = opnd<OV>(L);
     if constexpr ((OU >> 4) == OP_AUX) {  // an argument: agent or name at run time
-      if (u >= 0) { const int t = u; u = v; v = t; }
+      const bool sw = u >= 0;
+      const int t = u;
+      u = sw ? v : u;
+      v = sw ? t : v;
     }
   }
 }
@@ -626,20 +629,17 @@ __device__ __forceinline__ void decide_links(const Lane &L, gint *bind, unsigned
       int u, v;
       link_sides<R, J>(L, u, v);
       const int o = opaque(eo[J]);
-      bool chain = false;
-      if (u >= 0) {
-        pu[J] = u;
-        pv[J] = v;
-      } else if (u == v) {
-        loops++;
-      } else if (o != EMPTY) {
-        if (o >= 0 && (K::v_agent || v >= 0)) {
-          pu[J] = o;
-          pv[J] = v;
-        } else {
-          chain = true;
-        }
-      }
+      // the cases as selects, not nested branches (each divergent branch
+      // costs exec-mask updates): both sides agents; a closed loop; the
+      // exchange met an agent (a pair) or a name (a chain); else parked
+      const bool direct = u >= 0;
+      const bool loop = !direct && u == v;
+      const bool met = !direct && !loop && o != EMPTY;
+      const bool pair = met && o >= 0 && (K::v_agent || v >= 0);
+      const bool chain = met && !pair;
+      pu[J] = direct ? u : (pair ? o : -1);
+      pv[J] = v;
+      loops += loop ? 1 : 0;
       if (ballot(chain)) {
         if (chain) {
           int ou = -1, ov = 0;
