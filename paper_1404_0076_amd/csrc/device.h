@@ -690,14 +690,16 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
   // the lane's rule; -1 when it has none, or when its group could not be
   // allocated (the second walk then leaves it alone)
   int rid = act ? (code >> 1) : -1;
+  // the pair in the rule's orientation (selects, not a divergent branch)
+  const bool sw = act && (code & 1);
   Lane L;
-  L.a = a; L.b = b; L.pa0 = pa0; L.pa1 = pa1; L.pb0 = pb0; L.pb1 = pb1;
+  L.a = sw ? b : a;
+  L.b = sw ? a : b;
+  L.pa0 = sw ? pb0 : pa0;
+  L.pb0 = sw ? pa0 : pb0;
+  L.pa1 = sw ? pb1 : pa1;
+  L.pb1 = sw ? pa1 : pb1;
   L.my_a = 0; L.my_n = 0;
-  if (act && (code & 1)) {
-    L.a = b; L.b = a;
-    L.pa0 = pb0; L.pb0 = pa0;
-    L.pa1 = pb1; L.pb1 = pa1;
-  }
   // exchange results, one register per (rule, link): exchanges of different
   // rules are then in flight together without write-after-write waits
   // (written by the first walk for every lane of the rule's group, and read
@@ -796,15 +798,25 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
   }
   if (tot) {
     int base = C.append(tot);
+    if (base + tot <= QCAP) {  // all in the LDS tile: one store per new pair
 #pragma unroll
-    for (int j = 0; j < MAXL; j++) {
-      if (pu[j] >= 0) {
-        const int i = base + count_below(m[j]);
-        if (i < QCAP) nq_l[i] = mkpair(pu[j], pv[j]);
-        else if (i < D.qcap) *at2(nq_g, (unsigned)i) = pk(pu[j], pv[j]);
-        else lane_err = true;
+      for (int j = 0; j < MAXL; j++) {
+        if (m[j]) {
+          if (pu[j] >= 0) nq_l[base + count_below(m[j])] = mkpair(pu[j], pv[j]);
+          base += __popcll(m[j]);
+        }
       }
-      base += __popcll(m[j]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < MAXL; j++) {
+        if (pu[j] >= 0) {
+          const int i = base + count_below(m[j]);
+          if (i < QCAP) nq_l[i] = mkpair(pu[j], pv[j]);
+          else if (i < D.qcap) *at2(nq_g, (unsigned)i) = pk(pu[j], pv[j]);
+          else lane_err = true;
+        }
+        base += __popcll(m[j]);
+      }
     }
   }
   if (loops) atomicAdd(s_loops, loops);
