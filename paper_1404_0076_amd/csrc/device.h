@@ -486,19 +486,6 @@ __device__ __forceinline__ int opaque(int v) {
   return v;
 }
 
-__device__ __forceinline__ Lane opaque(const Lane &L) {
-  Lane o;
-  o.a = opaque(L.a);
-  o.b = opaque(L.b);
-  o.pa0 = opaque(L.pa0);
-  o.pa1 = opaque(L.pa1);
-  o.pb0 = opaque(L.pb0);
-  o.pb1 = opaque(L.pb1);
-  o.my_a = opaque(L.my_a);
-  o.my_n = opaque(L.my_n);
-  return o;
-}
-
 // the engine's counters: LDS words shared by the waves of the workgroup, or
 // wave-uniform registers when the engine is one wave
 template <bool SOLO>
@@ -725,7 +712,7 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
             *C.status = ST_ENOMEM;  // the step ends with ENOMEM; this lane issues nothing
             rid = -1;
           } else {
-            Lane X = opaque(L);
+            Lane X = L;
             X.my_a = ma;
             X.my_n = mn;
             L.my_a = X.my_a;
@@ -754,7 +741,7 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
         }
         if (mine) {
           const int rank = count_below(gm);
-          Lane X = opaque(L);
+          Lane X = L;
           X.my_a = ba + nalloc * rank;
           X.my_n = bn + nfresh * rank;
           L.my_a = X.my_a;
@@ -775,7 +762,7 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
   for_rules<0>(rid, ballot(rid >= 0), [&](auto ic, unsigned long long) {
     constexpr int R = decltype(ic)::value;
     if (rid == R)
-      decide_links<R, 0, MAXL>(opaque(L), bind, (unsigned)D.name_cap, eo[R], pu, pv, loops, bad);
+      decide_links<R, 0, MAXL>(L, bind, (unsigned)D.name_cap, eo[R], pu, pv, loops, bad);
   });
   // append the wave's new active pairs
   if constexpr (LANE) {
