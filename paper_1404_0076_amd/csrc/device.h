@@ -478,9 +478,9 @@ __device__ __forceinline__ int opnd(const Lane &L) {
   }
 }
 
-// an opaque copy: address arithmetic and tests on the value then stay inside
-// the rule code that uses them (otherwise they are hoisted out of the walk,
-// for every operand of every rule, and their masks spill)
+// an opaque copy: the compiler cannot see through it, so tests on the value
+// are not hoisted out of the rule code that uses them, and code after the
+// copy does not wait again on the memory operation that produced the value
 __device__ __forceinline__ int opaque(int v) {
   asm volatile("" : "+v"(v));
   return v;
