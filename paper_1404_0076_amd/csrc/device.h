@@ -517,8 +517,7 @@ struct Ctr<true> {
   __device__ __forceinline__ void fail_uniform(int, int) { err = ST_ENOMEM; }
   // wave-uniform call: a lane out of queue space, or a broken chain invariant
   __device__ __forceinline__ void fail(bool nomem, bool internal) {
-    if (ballot(internal)) err = ST_EINTERNAL;
-    else if (ballot(nomem)) err = ST_ENOMEM;
+    if (ballot(nomem || internal)) err = ballot(internal) ? ST_EINTERNAL : ST_ENOMEM;
   }
 };
 
@@ -651,7 +650,7 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
                                             int pa1, int pb0, int pb1, const NetDesc &D,
                                             gint *agent, gint *bind,
                                             gint2 *stuck, const int *rule_of, Pair *nq_l,
-                                            gint2 *nq_g, Ctr<SOLO> &C, int *s_loops,
+                                            gint2 *nq_g, Ctr<SOLO> &C, int &loops_lane,
                                             unsigned &rc_lane) {
   const int lane = __lane_id();
   const int code = rule_of[valid ? la * rt::NS + lb : 0];
@@ -785,11 +784,14 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
   }
   if (tot) {
     int base = C.append(tot);
-    if (base + tot <= QCAP) {  // all in the LDS tile: one store per new pair
+    if (base + tot <= QCAP) {
+      // all in the LDS tile: one store per link slot and lane, without a
+      // branch (a lane without a pair on the slot writes its spare slot)
 #pragma unroll
       for (int j = 0; j < MAXL; j++) {
         if (m[j]) {
-          if (pu[j] >= 0) nq_l[base + count_below(m[j])] = mkpair(pu[j], pv[j]);
+          const int i = pu[j] >= 0 ? base + count_below(m[j]) : QCAP + lane;
+          nq_l[i] = mkpair(pu[j], pv[j]);
           base += __popcll(m[j]);
         }
       }
@@ -806,7 +808,7 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
       }
     }
   }
-  if (loops) atomicAdd(s_loops, loops);
+  loops_lane += loops;
   C.fail(lane_err, bad);
 }
 
@@ -846,7 +848,7 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
                                             int *counter, const int *__restrict__ g_rules,
                                             int ns, int nr, unsigned max_steps, int flags) {
   extern __shared__ int s_rules[];
-  __shared__ Pair q[2][QCAP];
+  __shared__ Pair q[2][QCAP + 64];  // + a spare slot per lane (append)
   __shared__ int s_cnt[3];
   __shared__ int s_net;
   __shared__ int s_agent_top, s_name_top, s_status, s_nstuck, s_loops, s_maxf;
@@ -923,6 +925,7 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
       // its counters are shared words, so it always steps as a group
       constexpr bool LANE = ENGINE == 4;
       unsigned rc_lane = 0;  // lane r of each wave: interactions of rule r in this launch
+      int loops_lane = 0;    // closed loops dropped by this lane
       // Steps of wave 0 alone, while the frontier holds at most `limit` pairs:
       // the counters live in registers and no barrier separates steps (a
       // wave's own memory operations are performed in order).  The other waves
@@ -950,7 +953,7 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
             fetch_pair<64, QCAP>(base, n, tid, cq_l, cq_g, agent, valid, a, b, la, lb, pa0, pa1,
                                  pb0, pb1);
             pass_static<QCAP, MAXL, true, false>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, agent, bind,
-                                          stuck, rule_of, nq_l, nq_g, C, &s_loops, rc_lane);
+                                          stuck, rule_of, nq_l, nq_g, C, loops_lane, rc_lane);
           }
           // lanes of one wave need no cache action or wait to see each
           // other's writes (wavefront scope); the fence only keeps the
@@ -977,6 +980,7 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
         __syncthreads();
         solo(0x7fffffff);
         if (rc_lane) atomicAdd(&s_rc[tid], (unsigned long long)rc_lane);
+        if (loops_lane) atomicAdd(&s_loops, loops_lane);
         __syncthreads();
       } else {
         // a wider engine: all waves step together while the frontier is wider
@@ -1015,13 +1019,14 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
                                  pb0, pb1);
             pass_static<QCAP, MAXL, false, LANE>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, agent,
                                            bind, stuck, rule_of, nq_l, nq_g, C,
-                                           &s_loops, rc_lane);
+                                           loops_lane, rc_lane);
           }
           steps++;
           cur ^= 1;
           ci = cn;
         }
         if (rc_lane) atomicAdd(&s_rc[__lane_id()], (unsigned long long)rc_lane);
+        if (loops_lane) atomicAdd(&s_loops, loops_lane);
         __syncthreads();
       }
     } else
