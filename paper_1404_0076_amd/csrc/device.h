@@ -533,6 +533,16 @@ struct Ctr<false> {
   __device__ __forceinline__ int names(int n, int lane, int lead) { return take(name_top, n, lane, lead); }
   __device__ __forceinline__ int append(int n) { return take(next, n, __lane_id(), 0); }
   __device__ __forceinline__ int stuck(int n) { return take(nstuck, n, __lane_id(), 0); }
+  // agents and names for a whole wave, both atomics in flight together
+  __device__ __forceinline__ void agents_names(int na, int nn, int &ba, int &bn) {
+    int a = 0, b = 0;
+    if (__lane_id() == 0) {
+      if (na) a = atomicAdd(agent_top, na);
+      if (nn) b = atomicAdd(name_top, nn);
+    }
+    ba = __builtin_amdgcn_readlane(a, 0);
+    bn = __builtin_amdgcn_readlane(b, 0);
+  }
   __device__ __forceinline__ void fail_uniform(int lane, int lead) {
     if (lane == lead) *status = ST_ENOMEM;
   }
@@ -694,6 +704,18 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
   int pu[MAXL], pv[MAXL];  // new active pair of link j, pu[j] < 0 if none
 #pragma unroll
   for (int j = 0; j < MAXL; j++) { pu[j] = -1; pv[j] = 0; }
+  // a wave of a wider engine reserves the agents and cells of all its rule
+  // groups at once (one pair of LDS atomics, not one per rule group)
+  int wa = 0, wn = 0;
+  if constexpr (!SOLO && !LANE) {
+    int need_a = 0, need_n = 0;
+    for_rules<0>(rid, ballot(rid >= 0), [&](auto ic, unsigned long long gm) {
+      constexpr int R = decltype(ic)::value;
+      need_a += rt::T[R][RT_NALLOC] * __popcll(gm);
+      need_n += rt::T[R][RT_NFRESH] * __popcll(gm);
+    });
+    if (need_a | need_n) C.agents_names(need_a, need_n, wa, wn);
+  }
   // first walk: allocate, write the new agents, issue the exchanges
   for_rules<0>(rid, ballot(rid >= 0), [&](auto ic, unsigned long long gm) {
       constexpr int R = decltype(ic)::value;
@@ -725,8 +747,15 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
       } else {
         const int lead = __builtin_ctzll(gm);
         int ba = 0, bn = 0;
-        if constexpr (nalloc > 0) ba = C.agents(nalloc * cnt, lane, lead);
-        if constexpr (nfresh > 0) bn = C.names(nfresh * cnt, lane, lead);
+        if constexpr (SOLO) {
+          if constexpr (nalloc > 0) ba = C.agents(nalloc * cnt, lane, lead);
+          if constexpr (nfresh > 0) bn = C.names(nfresh * cnt, lane, lead);
+        } else {
+          ba = wa;
+          bn = wn;
+          wa += nalloc * cnt;
+          wn += nfresh * cnt;
+        }
         // interactions per rule: lane R of the wave counts rule R (the lane id
         // is opaque so that the test is not hoisted, per rule, out of the loop)
         rc_lane += opaque(lane) == R ? (unsigned)cnt : 0u;
