@@ -529,8 +529,6 @@ struct Ctr<false> {
     if (lane == lead) b = atomicAdd(p, n);
     return __builtin_amdgcn_readlane(b, lead);
   }
-  __device__ __forceinline__ int agents(int n, int lane, int lead) { return take(agent_top, n, lane, lead); }
-  __device__ __forceinline__ int names(int n, int lane, int lead) { return take(name_top, n, lane, lead); }
   __device__ __forceinline__ int append(int n) { return take(next, n, __lane_id(), 0); }
   __device__ __forceinline__ int stuck(int n) { return take(nstuck, n, __lane_id(), 0); }
   // agents and names for a whole wave, both atomics in flight together
