@@ -122,6 +122,38 @@ def cpu_baseline(R, net_list, seconds):
                       f"{dt:.1f} s, single thread"}
 
 
+_POOL_JOB = None  # (rules, nets) shared with forked workers
+
+
+def _oracle_share(k, workers):
+    import oracle
+    R, net_list = _POOL_JOB
+    return sum(int(oracle.reduce(R, net_list[i]).interactions)
+               for i in range(k, len(net_list), workers))
+
+
+def cpu_baseline_parallel(R, net_list):
+    """The oracle over the whole batch in independent processes, one per host
+    core of this GPU's share (at most 16).  Runs before anything touches the
+    GPU, so the workers are plain forks of a process without a GPU context."""
+    import multiprocessing as mp
+    global _POOL_JOB
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    workers = max(1, min(16, cores))
+    _POOL_JOB = (R, net_list)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        tot = sum(pool.starmap(_oracle_share, [(k, workers) for k in range(workers)]))
+    dt = time.perf_counter() - t0
+    _POOL_JOB = None
+    return {"value": tot / dt, "unit": "interactions/s", "cores": workers, "kind": "oracle",
+            "sample": f"all {len(net_list)} nets, {tot} interactions, {dt:.2f} s, "
+                      f"{workers} processes (nets dealt round-robin)"}
+
+
 def bench_serve(args, P, R, nets, torch):
     """Served workload: Poisson arrivals of nets drawn from the batch mix."""
     from paper_1404_0076_amd.serve import serve
@@ -251,6 +283,14 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(nets are independent; see DESIGN.md for how the batch would shard)", file=sys.stderr)
         sys.exit(2)
+
+    par_baseline = None
+    if args.workload == "batch" and not args.no_cpu_baseline and not args.copy_calibration:
+        # the oracle on all host cores, before the GPU is initialised
+        from paper_1404_0076_amd import nets as _nets
+        log("cpu baseline (parallel)")
+        par_baseline = cpu_baseline_parallel(_nets.arith_rules(),
+                                             _nets.config4_batch(seed=args.seed, n_nets=args.n_nets))
 
     import torch
 
@@ -407,6 +447,8 @@ def main():
         ordered = [net_list[i] for i in order] if args.workload == "batch" else net_list
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(R, ordered, args.cpu_seconds)
+    if par_baseline is not None:
+        out["cpu_baseline_parallel"] = par_baseline
     print(json.dumps(out), flush=True)
 
 
