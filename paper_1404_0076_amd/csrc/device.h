@@ -653,13 +653,15 @@ __device__ __forceinline__ void decide_links(const Lane &L, gint *bind, unsigned
 // merge of result arrays): every lane reserves its own agents, cells and
 // frontier entries with one atomic each, instead of one reservation per rule
 // group of a wave ranked by mask counts
-template <int QCAP, int MAXL, bool SOLO, bool LANE>
+// HOLD (one-wave steps): the lane keeps its first new active pair in
+// registers (ha, hb; ha < 0 if none) and appends only the others
+template <int QCAP, int MAXL, bool SOLO, bool LANE, bool HOLD = false>
 __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, int lb, int pa0,
                                             int pa1, int pb0, int pb1, const NetDesc &D,
                                             gint *agent, gint *bind,
                                             gint2 *stuck, const int *rule_of, Pair *nq_l,
                                             gint2 *nq_g, Ctr<SOLO> &C, int &loops_lane,
-                                            unsigned &rc_lane) {
+                                            unsigned &rc_lane, int &ha, int &hb) {
   const int lane = __lane_id();
   const int code = rule_of[valid ? la * rt::NS + lb : 0];
   // take the loaded ports through a copy on every path: later rule blocks then
@@ -790,6 +792,18 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
     if (rid == R)
       decide_links<R, 0, MAXL>(L, bind, (unsigned)D.name_cap, eo[R], pu, pv, loops, bad);
   });
+  if constexpr (HOLD) {
+    int h_a = -1, h_b = 0;
+#pragma unroll
+    for (int j = 0; j < MAXL; j++) {
+      const bool take = h_a < 0 && pu[j] >= 0;
+      h_a = take ? pu[j] : h_a;
+      h_b = take ? pv[j] : h_b;
+      pu[j] = take ? -1 : pu[j];
+    }
+    ha = h_a;
+    hb = h_b;
+  }
   // append the wave's new active pairs
   if constexpr (LANE) {
 #pragma unroll
@@ -958,6 +972,10 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
       // wave's own memory operations are performed in order).  The other waves
       // of a wider engine wait at the caller's barrier meanwhile.  On return
       // the state is back in LDS, with the frontier count in s_cnt[ci].
+      // While the pairs of a step fit the wave, each lane keeps its first new
+      // pair in registers for the next step (no LDS round trip); only the
+      // others go through the LDS frontier, and lanes without a pair take
+      // them by rank.  Wider steps run from the LDS frontier in chunks.
       auto solo = [&](int limit) {
         Ctr<true> C;
         C.agent_top = __builtin_amdgcn_readfirstlane(s_agent_top);
@@ -965,22 +983,61 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
         C.nstuck = __builtin_amdgcn_readfirstlane(s_nstuck);
         C.err = __builtin_amdgcn_readfirstlane(s_status);
         C.next = 0;
-        int n = __builtin_amdgcn_readfirstlane(s_cnt[ci]);
+        int n = __builtin_amdgcn_readfirstlane(s_cnt[ci]);  // pairs in the frontier q[cur]
         int maxf = __builtin_amdgcn_readfirstlane(s_maxf);
-        while (n > 0 && n <= limit && C.err >= 0 && steps < stop) {
-          if (n > maxf) maxf = n;
+        int ha = -1, hb = 0;  // the lane's held pair (ha < 0: none)
+        int nh = 0;           // held pairs of the wave
+        // the held pairs back into the frontier, after its n pairs
+        auto release = [&]() {
+          if (nh) {
+            const unsigned long long hm = ballot(ha >= 0);
+            bool over = false;
+            if (ha >= 0) {
+              const int i = n + count_below(hm);
+              if (i < QCAP) q[cur][i] = mkpair(ha, hb);
+              else if (i < D.qcap) *at2(cur ? queue1 : queue0, (unsigned)i) = pk(ha, hb);
+              else over = true;
+            }
+            C.fail(over, false);
+            n += nh;
+            nh = 0;
+            ha = -1;
+          }
+        };
+        for (;;) {
+          const int tot = n + nh;
+          if (!(tot > 0 && tot <= limit && C.err >= 0 && steps < stop)) break;
+          if (tot > maxf) maxf = tot;
           const Pair *cq_l = q[cur];
           const gint2 *cq_g = cur ? queue1 : queue0;
           Pair *nq_l = q[cur ^ 1];
           gint2 *nq_g = cur ? queue0 : queue1;
           C.next = 0;
-          for (int base = 0; base < n; base += 64) {
-            bool valid;
-            int a, b, la, lb, pa0, pa1, pb0, pb1;
-            fetch_pair<64, QCAP>(base, n, tid, cq_l, cq_g, agent, valid, a, b, la, lb, pa0, pa1,
-                                 pb0, pb1);
-            pass_static<QCAP, MAXL, true, false>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, agent, bind,
-                                          stuck, rule_of, nq_l, nq_g, C, loops_lane, rc_lane);
+          int nha = -1, nhb = 0;
+          if (tot <= 64) {
+            // held pairs stay with their lanes; the n frontier pairs (all in
+            // the LDS tile: n <= 64) go to the free lanes by rank
+            const int r = count_below(ballot(ha < 0));
+            const bool take = ha < 0 && r < n;
+            const Pair rx = cq_l[take ? r : 0];
+            const bool valid = ha >= 0 || take;
+            const int a = ha >= 0 ? ha : (take ? rx.x : 0);
+            const int b = ha >= 0 ? hb : (take ? rx.y : 0);
+            const v4i ra = *rec(agent, (unsigned)a), rb = *rec(agent, (unsigned)b);
+            pass_static<QCAP, MAXL, true, false, true>(valid, a, b, ra.x, rb.x, ra.y, ra.z, rb.y,
+                                                       rb.z, D, agent, bind, stuck, rule_of, nq_l,
+                                                       nq_g, C, loops_lane, rc_lane, nha, nhb);
+          } else {
+            release();
+            for (int base = 0; base < n; base += 64) {
+              bool valid;
+              int a, b, la, lb, pa0, pa1, pb0, pb1;
+              fetch_pair<64, QCAP>(base, n, tid, cq_l, cq_g, agent, valid, a, b, la, lb, pa0,
+                                   pa1, pb0, pb1);
+              pass_static<QCAP, MAXL, true, false>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D,
+                                                   agent, bind, stuck, rule_of, nq_l, nq_g, C,
+                                                   loops_lane, rc_lane, nha, nhb);
+            }
           }
           // lanes of one wave need no cache action or wait to see each
           // other's writes (wavefront scope); the fence only keeps the
@@ -989,7 +1046,11 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
           steps++;
           cur ^= 1;
           n = C.next;
+          ha = nha;
+          hb = nhb;
+          nh = __popcll(ballot(ha >= 0));
         }
+        release();  // the frontier whole in q[cur] again, for the caller
         if (tid == 0) {
           s_cnt[ci] = n;
           s_cnt[ci == 2 ? 0 : ci + 1] = 0;
@@ -1044,9 +1105,10 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
             int a, b, la, lb, pa0, pa1, pb0, pb1;
             fetch_pair<WG, QCAP>(base, n, tid, cq_l, cq_g, agent, valid, a, b, la, lb, pa0, pa1,
                                  pb0, pb1);
+            int nha, nhb;
             pass_static<QCAP, MAXL, false, LANE>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, agent,
                                            bind, stuck, rule_of, nq_l, nq_g, C,
-                                           loops_lane, rc_lane);
+                                           loops_lane, rc_lane, nha, nhb);
           }
           steps++;
           cur ^= 1;
