@@ -12,19 +12,22 @@
 // the loop body of evaluate() (Section 3.6):
 //   int  -- every lane takes one active pair, looks its rule up in the LDS
 //           rule table, allocates the right-hand side's agents and names with
-//           a wave-wide prefix sum and one LDS atomic per wave (the scan-based
-//           output allocation proposed in Section 4.2), writes the new agents
-//           into the int32 SoA heap, reusing the two slots of the pair;
+//           a wave-level scan (mask prefix counts, or a prefix sum in the
+//           per-lane interpreter) and one counter update per wave (the
+//           scan-based output allocation proposed in Section 4.2), and writes
+//           the new agents as 16-byte records {label, port0, port1, -},
+//           reusing the two slots of the pair;
 //   com  -- each equation left by the rule is linked: a name side exchanges
 //           the other side into the name's cell; the lane that finds the cell
 //           already filled owns the second occurrence, forms the equation
 //           (parked value = other side) and carries on along the chain; an
 //           equation between two agents is a new active pair;
 //   compaction -- new active pairs are appended to the next frontier with a
-//           wave ballot, a mask prefix count and one LDS atomic per wave.
-// A single workgroup barrier separates consecutive steps.  After the loop,
-// name-to-name chains left in the cells (the partial com of the remark after
-// the correctness proposition of Section 3.6) are compressed by pointer
+//           wave ballot, a mask prefix count and one counter update per wave.
+// Engines of several waves separate steps with one workgroup barrier; a
+// single wave needs none (its memory operations are ordered).  After the
+// loop, name-to-name chains left in the cells (the partial com of the remark
+// after the correctness proposition of Section 3.6) are compressed by pointer
 // jumping.
 #ifndef INET_DEVICE_H
 #define INET_DEVICE_H

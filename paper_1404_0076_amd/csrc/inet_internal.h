@@ -2,7 +2,9 @@
 // HIP kernels of the evaluator (not part of the public ABI).
 //
 // A net lives in its own region of the caller's device buffer:
-//   label[agent_cap], port0[agent_cap], port1[agent_cap]   agent heap (SoA int32)
+//   agent[agent_cap][4]   agent heap: one 16-byte record {label, port0, port1,
+//                         unused} per slot, so that a pair's two agents are
+//                         two 16-byte loads
 //   bind[name_cap]                                        one cell per name
 //   queue[2][qcap]    frontier double buffer: entries >= LDS capacity of the
 //                     running engine spill here; the saved frontier lives here
