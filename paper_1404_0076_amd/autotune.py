@@ -22,7 +22,11 @@ CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache
 WIDTHS = (64, 128, 256, 512, 1024)
 ENGINES = (2, 3, 4)  # rule-uniform, rules compiled in, and that with atomic append
 # (engine 1 is never faster)
-RESIDENTS = (0, 256)  # as many engines as fit, or one per compute unit
+# caps on resident engines: as many as fit, one per compute unit, or fewer
+# (a batch whose time is one net's critical path runs that path a little
+# faster with fewer engines beside it, as long as the others still finish
+# within it)
+RESIDENTS = (0, 64, 128, 256)
 
 
 def workload_signature(net_list: Sequence) -> str:
