@@ -652,7 +652,7 @@ static int readback_subst(St *s, int32_t *n_cycles) {
       if (kind == 2) s->n_col++; else if (kind == 1) s->n_sub++; else s->n_com++;
       done = 1;
     }
-    if (!done && s->ealive[e]) cycles++;
+    if (!done && s->ealive[e] && ORC_MUTANT != 7) cycles++;
   }
   *n_cycles = cycles;
   free(grp); free(uf); free(stk);
@@ -711,6 +711,11 @@ static int cmp_seq(const int32_t *a, int64_t na, const int32_t *b, int64_t nb) {
 
 static int cmp_res(const void *pa, const void *pb) {
   const Res *a = (const Res *)pa, *b = (const Res *)pb;
+  if (ORC_MUTANT == 6) { /* planted: right sides compared first */
+    int c = cmp_seq(g_keys + a->kr, a->nr, g_keys + b->kr, b->nr);
+    if (c) return c;
+    return cmp_seq(g_keys + a->kl, a->nl, g_keys + b->kl, b->nl);
+  }
   int c = cmp_seq(g_keys + a->kl, a->nl, g_keys + b->kl, b->nl);
   if (c) return c;
   return cmp_seq(g_keys + a->kr, a->nr, g_keys + b->kr, b->nr);
@@ -740,7 +745,8 @@ static int serialise(St *s, Buf *out, int32_t *n_stuck) {
     int64_t a1 = keys.n;
     encode(s, s->er[e], NULL, NULL, &keys, &stk);
     int64_t a2 = keys.n;
-    if (cmp_seq(keys.v + a0, a1 - a0, keys.v + a1, a2 - a1) <= 0) {
+    const int ord = cmp_seq(keys.v + a0, a1 - a0, keys.v + a1, a2 - a1);
+    if (ORC_MUTANT == 5 ? ord >= 0 : ord <= 0) { /* 5: planted, larger side first */
       R->l = s->el[e]; R->r = s->er[e];
       R->kl = a0; R->nl = a1 - a0; R->kr = a1; R->nr = a2 - a1;
     } else {

@@ -592,13 +592,48 @@ struct LinkKind {
   static constexpr bool both_new = (OU >> 4) == OP_NEW && (OV >> 4) == OP_NEW;
   // after link_sides, a v that survives the "both agents" test is an agent
   static constexpr bool v_agent = (OU >> 4) == OP_NEW || (OV >> 4) == OP_NEW;
+  // a link whose name side is one of the rule's fresh names: folding leaves
+  // a bound name at the top of an equation only in x = C[x] (its other
+  // occurrence is inside the new agent C), so the cell was allocated by this
+  // very interaction and is empty: the link parks C there without an exchange
+  static constexpr bool fresh = (OU >> 4) == OP_FRESH || (OV >> 4) == OP_FRESH;
 };
 
-// first walk, links: issue the exchange of every link whose name side is a name
+// fresh name F of rule R is the name side of one of its links (the cell then
+// receives the parked term instead of EMPTY)
+template <int R, int F, int J = 0>
+constexpr bool fresh_linked() {
+  if constexpr (J >= rt::T[R][RT_NEQ] || J >= MAXEQ) {
+    return false;
+  } else {
+    constexpr int OU = rt::T[R][RT_EQ + 2 * J], OV = rt::T[R][RT_EQ + 2 * J + 1];
+    constexpr int FC = (OP_FRESH << 4) | F;
+    if constexpr (OU == FC || OV == FC) return true;
+    else return fresh_linked<R, F, J + 1>();
+  }
+}
+
+// initialise the rule's fresh name cells: EMPTY, except a cell that a link of
+// the same interaction parks its term in (issue_links writes that one)
+template <int R, int F>
+__device__ __forceinline__ void st_fresh(const Lane &L, gint *bind) {
+  if constexpr (F < rt::T[R][RT_NFRESH]) {
+    if constexpr (!fresh_linked<R, F>()) *at(bind, (unsigned)(L.my_n + F)) = EMPTY;
+    st_fresh<R, F + 1>(L, bind);
+  }
+}
+
+// first walk, links: issue the exchange of every link whose name side is a
+// name (a fresh name's cell is written directly: it holds nothing yet)
 template <int R, int J, int MAXL>
 __device__ __forceinline__ void issue_links(const Lane &L, gint *bind, int (&eo)[MAXL]) {
   if constexpr (J < rt::T[R][RT_NEQ] && J < MAXL) {
-    if constexpr (!LinkKind<R, J>::both_new) {
+    if constexpr (LinkKind<R, J>::fresh) {
+      int u, v;
+      link_sides<R, J>(L, u, v);
+      *at(bind, (unsigned)~u) = v;
+      eo[J] = EMPTY;
+    } else if constexpr (!LinkKind<R, J>::both_new) {
       int u, v;
       link_sides<R, J>(L, u, v);
       int e = EMPTY;
@@ -743,8 +778,7 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
             L.my_n = X.my_n;
             issue_links<R, 0, MAXL>(X, bind, eo[R]);
             st_agents<R, 0>(X, agent);
-#pragma unroll
-            for (int f = 0; f < nfresh; f++) *at(bind, (unsigned)(X.my_n + f)) = EMPTY;
+            st_fresh<R, 0>(X, bind);
           }
         }
       } else {
@@ -779,11 +813,12 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
           L.my_n = X.my_n;
           // the exchanges first, so that they are in flight while the new
           // agents and cells are written (a lane reads agent records only at
-          // the next step, and no link of this step names a fresh cell)
+          // the next step; an exchange never targets a fresh cell of the same
+          // interaction: a link on one parks its term with a plain store, and
+          // st_fresh leaves that cell alone)
           issue_links<R, 0, MAXL>(X, bind, eo[R]);
           st_agents<R, 0>(X, agent);
-#pragma unroll
-          for (int f = 0; f < nfresh; f++) *at(bind, (unsigned)(X.my_n + f)) = EMPTY;
+          st_fresh<R, 0>(X, bind);
         }
       }
   });

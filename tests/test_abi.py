@@ -46,6 +46,24 @@ def test_rule_templates_after_folding():
     assert info["bytes"].tolist() == [68, 32, 88, 48, 88, 48, 32, 16, 40, 40, 40, 96]
 
 
+# a right-hand side that keeps x = C[x]: folding cannot move C into the other
+# occurrence of x (it is inside C), so the equation stays as a link whose name
+# side is a fresh name
+CYCLE_SIG = nets.Signature(["P", "Q", "S", "Z", "D"], [1, 1, 1, 0, 2])
+CYCLE_RULES = ["P(a) = Q(b) -> a = b, x = S(x)", "D(p, q) = Z -> p = Z, q = Z",
+               "P(a) = Z -> y = D(y, a)"]
+
+
+def test_cycle_rule_keeps_fresh_link():
+    rules = nets.parse_rules(CYCLE_SIG, CYCLE_RULES)
+    info = P.rules_check(rules)
+    assert info["n_new"].tolist() == [1, 2, 1]
+    assert info["n_fresh"].tolist() == [1, 0, 1]
+    assert info["n_links"].tolist() == [2, 2, 1]
+    rc, nbytes, log = P.jit_build(rules, "gfx950")
+    assert rc == P.OK, log
+
+
 @pytest.mark.parametrize("texts", [
     ["Add(y,r) = S(x) -> Add(y,y) = x, r = S(w)"],
     ["Add(y,r) = S(x) -> r = S(x)", "Add(a,b) = S(c) -> a = S(c), b = Z"],

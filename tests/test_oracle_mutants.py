@@ -1,6 +1,8 @@
 """Planted mistakes in the oracle (built on the CPU with -DORC_MUTANT=k) must
 each be caught by the pins: a transposed operand, a lost orientation swap, a
-dropped right-hand-side equation, com counted as an interaction."""
+dropped right-hand-side equation, com counted as an interaction, residuals
+oriented larger side first, residuals sorted by their right sides first, and
+name cycles not counted."""
 import os
 import subprocess
 import sys
@@ -35,6 +37,9 @@ def _pins_hold(lib):
     r = oracle.reduce(nets.add_rules(), nets.parse_net(nets.ARITH_SIG, "<r | S(Z) = Add(Z, r)>"),
                       lib=lib)
     checks.append(r.nf.tolist() == [1, 1, 0, 0] and r.interactions == 2)
+    # stream conventions: residual orientation and order, cycles counted
+    import test_oracle_residuals as tr
+    checks += [tr.case_holds(c, lib=lib) for c in tr.cases()]
     return all(checks)
 
 
@@ -42,7 +47,7 @@ def test_correct_oracle_passes_pins():
     assert _pins_hold(oracle._load())
 
 
-@pytest.mark.parametrize("mutant", [1, 2, 3, 4])
+@pytest.mark.parametrize("mutant", [1, 2, 3, 4, 5, 6, 7])
 def test_mutant_caught(mutant, tmp_path):
     # a planted mistake may also corrupt the oracle's state and crash it: the
     # pins run in a child process, and a crash counts as caught

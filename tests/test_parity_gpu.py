@@ -43,6 +43,23 @@ def test_paper_examples():
             assert res.steps == case["rounds"]
 
 
+RESIDUALS = os.path.join(os.path.dirname(__file__), "golden", "residuals_and_cycles.json")
+
+
+@pytest.mark.parametrize("engine", [0, 1, 2, 4])
+def test_residuals_and_cycles(engine):
+    # residual equations in the order and orientation worked out by hand, and
+    # name cycles left out of the stream
+    for case in json.load(open(RESIDUALS))["cases"]:
+        say("residuals", engine, case["net"])
+        net = nets.parse_net(nets.ARITH_SIG, case["net"])
+        res, nf, pr = g = gpu(R, net, engine=engine)
+        assert res.status == case["status"] and res.interactions == case["interactions"]
+        assert res.n_stuck == case["n_stuck"]
+        assert nf.tolist() == case["nf"]
+        assert_same(g, oracle_run(R, net), case["net"])
+
+
 SMALL = [
     "<r | Add(Z, r) = S(Z)>", "<r | Add(S(Z), r) = Z>", "<r | Mul(Z, r) = Z>",
     "<p, q | Dup(p, q) = Z>", "< | Era = Z>", "<r | Fib(r) = Z>", "<r | Fib2(r) = Z>",
@@ -131,7 +148,24 @@ def chain_net(length, free=False):
     return nets.parse_net(CHAIN_SIG, f"<{iface} | A(r) = x0, {links}x{length - 1} = {end}>")
 
 
+# rules whose right-hand side keeps x = C[x] (a fresh name parked at the top
+# of an equation, its other occurrence inside C), next to ordinary links
+CYCLE_SIG = nets.Signature(["P", "Q", "S", "Z", "D"], [1, 1, 1, 0, 2])
+CYCLE_RULES = ["P(a) = Q(b) -> a = b, x = S(x)", "D(p, q) = Z -> p = Z, q = Z",
+               "P(a) = Z -> y = D(y, a)"]
+
+
+def cycle_net(k):
+    # k rule applications of each kind, the results joined through names
+    eqs, iface = [], []
+    for i in range(k):
+        eqs += [f"P(r{i}) = Q(s{i})", f"P(u{i}) = Z", f"D(v{i}, w{i}) = Z"]
+        iface += [f"r{i}", f"s{i}", f"u{i}", f"v{i}", f"w{i}"]
+    return nets.parse_net(CYCLE_SIG, f"<{', '.join(iface)} | {', '.join(eqs)}>")
+
+
 OTHER_TABLES = [
+    ("cycle", CYCLE_SIG, CYCLE_RULES, [cycle_net(1), cycle_net(5), cycle_net(200)]),
     ("chain", CHAIN_SIG, ["A(r) = B -> r = C"],
      [chain_net(1), chain_net(5), chain_net(40), chain_net(3, free=True)]),
     ("loop", LOOP_SIG, ["P(a) = Q(b) -> a = b"],
