@@ -6,8 +6,11 @@ restore the loaded nets (device to device), reduce every net to normal form
 (int/com step loop, pointer jumping), with the inputs resident in HBM.
 
 Default workload: 4096 independent nets (Add trees, Mul, Fib; lognormal sizes,
-seed 0) reduced by one persistent launch.  --workload mul|fib|addtree times a
-single net instead.  Prints one JSON line.
+seed 0) reduced by one persistent launch; the same line carries the plain
+single-net evaluator on the three single-net workloads (single_net_configs) and
+the served stream at two arrival rates (served).  --workload
+mul|fib|addtree|ackermann|algae times one net instead, --workload serve one
+served rate.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -128,14 +131,15 @@ _POOL_JOB = None  # (rules, nets) shared with forked workers
 def _oracle_share(k, workers):
     import oracle
     R, net_list = _POOL_JOB
-    return sum(int(oracle.reduce(R, net_list[i]).interactions)
-               for i in range(k, len(net_list), workers))
+    return [(i, int(oracle.reduce(R, net_list[i]).interactions))
+            for i in range(k, len(net_list), workers)]
 
 
-def cpu_baseline_parallel(R, net_list):
-    """The oracle over the whole batch in independent processes, one per host
-    core of this GPU's share (at most 16).  Runs before anything touches the
-    GPU, so the workers are plain forks of a process without a GPU context."""
+def oracle_parallel(R, net_list, what="nets"):
+    """The oracle over every net of ``net_list`` in independent processes, one
+    per host core of this GPU's share (at most 16).  Runs before anything
+    touches the GPU, so the workers are plain forks of a process without a GPU
+    context.  Returns (baseline record, per-net interaction counts)."""
     import multiprocessing as mp
     global _POOL_JOB
     try:
@@ -144,40 +148,50 @@ def cpu_baseline_parallel(R, net_list):
         cores = os.cpu_count() or 1
     workers = max(1, min(16, cores))
     _POOL_JOB = (R, net_list)
+    counts = np.zeros(len(net_list), np.int64)
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(workers) as pool:
-        tot = sum(pool.starmap(_oracle_share, [(k, workers) for k in range(workers)]))
+        for part in pool.starmap(_oracle_share, [(k, workers) for k in range(workers)]):
+            for i, c in part:
+                counts[i] = c
     dt = time.perf_counter() - t0
     _POOL_JOB = None
-    return {"value": tot / dt, "unit": "interactions/s", "cores": workers, "kind": "oracle",
-            "sample": f"all {len(net_list)} nets, {tot} interactions, {dt:.2f} s, "
-                      f"{workers} processes (nets dealt round-robin)"}
+    tot = int(counts.sum())
+    rec = {"value": tot / dt, "unit": "interactions/s", "cores": workers, "kind": "oracle",
+           "sample": f"all {len(net_list)} {what}, {tot} interactions, {dt:.2f} s, "
+                     f"{workers} processes (nets dealt round-robin)"}
+    return rec, counts
 
 
-def bench_serve(args, P, R, nets, torch):
-    """Served workload: Poisson arrivals of nets drawn from the batch mix."""
+def cpu_baseline_parallel(R, net_list):
+    return oracle_parallel(R, net_list)[0]
+
+
+def measure_served(P, R, pool, caps, ref_counts, rate, duration, round_steps=256, wg=0,
+                   loop="native"):
+    """Serve a Poisson stream (rate nets/s for duration s, seed 3) of requests
+    drawn from ``pool`` with replacement (seed 4).  Latency = completion -
+    arrival (queueing included); sustained rate = completed interactions over
+    the loop's wall time.  The served interaction total is checked against
+    ``ref_counts`` (per pool net) for the picked entries."""
     from paper_1404_0076_amd.serve import serve
-    pool = nets.config5_pool(seed=2, n_nets=args.pool)
-    log(f"sizing pool of {len(pool)}")
-    used_a, used_n, steps, inter = size_batch(P, R, pool, args.wg or 64)
-    caps = list(zip(used_a + 64, used_n + 64))
-    arrivals = nets.poisson_arrivals(3, args.rate, args.duration)
+    arrivals = nets_mod().poisson_arrivals(3, rate, duration)
     rng = np.random.Generator(np.random.PCG64(4))
     pick = rng.integers(0, len(pool), len(arrivals))
-    log(f"serving {len(arrivals)} requests at {args.rate}/s")
-    if args.serve_loop == "native":
-        # the library's loop; per-request results stay numpy arrays
+    log(f"serving {len(arrivals)} requests at {rate:g}/s")
+    import torch
+    if loop == "native":
         srv = P.Server(R, 8192, 48 << 30)
-        srv.set_config(wg_size=args.wg)
-        res = srv.run(pool, arrivals, pick, caps=caps, round_steps=args.round_steps,
-                      time_limit=900.0, stream=torch.cuda.current_stream())
+        srv.set_config(wg_size=wg)
+        res = srv.run(pool, arrivals, pick, caps=caps, round_steps=round_steps, time_limit=900.0,
+                      stream=torch.cuda.current_stream())
         srv.free()
         status, inter_done = res["status"], res["interactions"].astype(np.int64)
         lat = (res["done"] - arrivals) * 1e3
         rounds, wall, max_res = res["rounds"], res["wall"], res["max_resident"]
     else:
         rep = serve(R, pool, arrivals, pick, caps=caps, max_slots=8192, workspace_bytes=48 << 30,
-                    round_steps=args.round_steps, wg_size=args.wg)
+                    round_steps=round_steps, wg_size=wg)
         status = np.array([x.status for x in rep.served])
         inter_done = np.array([x.interactions for x in rep.served], dtype=np.int64)
         lat = np.array([x.latency for x in rep.served]) * 1e3
@@ -186,22 +200,87 @@ def bench_serve(args, P, R, nets, torch):
     if bad:
         raise RuntimeError(f"{bad} requests failed")
     total = int(inter_done.sum())
-    assert total == int(inter[pick].sum()), "served interaction count differs from the sizing pass"
+    want = int(ref_counts[pick].sum())
+    if total != want:
+        raise RuntimeError(f"served {total} interactions, the reference counts give {want}")
+    return {"rate": rate, "duration_s": duration, "requests": int(len(arrivals)),
+            "interactions": total, "sustained": total / wall, "offered": total / duration,
+            "wall_s": wall, "rounds": int(rounds), "max_resident": int(max_res),
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "max": float(lat.max())},
+            "loop": loop}
+
+
+def nets_mod():
+    from paper_1404_0076_amd import nets
+    return nets
+
+
+def served_pool(P, R, nets, pool_size, wg=64, pool=None):
+    """The request pool and its exact capacities (one sizing pass)."""
+    if pool is None:
+        pool = nets.config5_pool(seed=2, n_nets=pool_size)
+    log(f"sizing pool of {len(pool)}")
+    used_a, used_n, steps, inter = size_batch(P, R, pool, wg)
+    caps = list(zip(used_a + 64, used_n + 64))
+    return pool, caps, inter
+
+
+def bench_serve(args, P, R, nets, torch, pool_ref=None, pool=None):
+    """Served workload: Poisson arrivals of nets drawn from the batch mix."""
+    pool, caps, inter = served_pool(P, R, nets, args.pool, args.wg or 64, pool)
+    ref, checked = inter, "the sizing pass"
+    if pool_ref is not None:
+        ref, checked = pool_ref[1], "the oracle"
+    rec = measure_served(P, R, pool, caps, ref, args.rate, args.duration, args.round_steps,
+                         args.wg, args.serve_loop)
     out = {
-        "metric": METRIC, "value": total / wall, "unit": "interactions/s",
-        "n_gpus": 1, "steps": rounds, "warmup": 0, "ms_per_step": wall * 1e3 / max(1, rounds),
+        "metric": METRIC, "value": rec["sustained"], "unit": "interactions/s",
+        "n_gpus": 1, "steps": rec["rounds"], "warmup": 0,
+        "ms_per_step": rec["wall_s"] * 1e3 / max(1, rec["rounds"]),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": f"served: Poisson arrivals at {args.rate:g} nets/s for {args.duration:g} s "
                                f"from a pool of {len(pool)} nets (batch mix, seed 2)",
-                   "round_steps": args.round_steps, "requests": len(arrivals),
+                   "round_steps": args.round_steps, "requests": rec["requests"],
                    "loop": args.serve_loop},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "max": float(lat.max())},
-        "offered_interactions_per_s": total / args.duration,
-        "rounds": rounds, "max_resident": max_res, "wall_s": wall,
+        "latency_ms": rec["latency_ms"],
+        "offered_interactions_per_s": rec["offered"],
+        "rounds": rec["rounds"], "max_resident": rec["max_resident"], "wall_s": rec["wall_s"],
+        "interactions_checked_against": checked,
     }
+    if pool_ref is not None:
+        out["cpu_baseline"] = pool_ref[0]
     print(json.dumps(out), flush=True)
+
+
+def time_single(P, R, net, wg=1024, reps=3, engine=0):
+    """The plain single-net evaluator on one net: exact capacities from a
+    sizing pass, then ``reps`` timed restore + reduce runs.  Returns
+    interactions/s over the wall time, the reduce kernel's mean time (HIP
+    events on the launch stream) and the algorithmic-byte roofline fraction."""
+    import torch
+    ua, un, st, it = size_batch(P, R, [net], wg, engine)
+    hs = P.batch_load(R, [net], agent_caps=ua + 64, name_caps=un + 64)
+    hs.set_config(wg_size=wg, engine=engine)
+    hs.reset(); hs.reduce_async(); torch.cuda.synchronize()
+    kms = []
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        hs.reset()
+        hs.reduce_async()
+        kms.append(hs.last_kernel_ms())
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t1) / reps
+    rs = hs.results()
+    assert rs[0].interactions == int(it[0]), "interaction count changed between runs"
+    alg = float(np.dot(hs.per_rule(0).astype(np.float64), hs.rule_bytes().astype(np.float64)))
+    kmean = float(np.mean(kms))
+    cfg = hs.get_config()
+    hs.free()
+    return {"value": float(it[0]) / dt, "ms": dt * 1000, "kernel_ms": kmean, "steps": int(st[0]),
+            "interactions": int(it[0]), "wg_size": cfg["wg_size"], "engine": cfg["engine"],
+            "roofline_frac": alg / (kmean * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
 def bench_pipeline(args, P, R, net_list, workload, used_a, used_n, inter, steps, torch):
@@ -268,7 +347,14 @@ def main():
                     help="pick engine width and variant with the autotuner (cached)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-single", action="store_true", help="skip the single-net side measurement")
+    ap.add_argument("--no-single", action="store_true",
+                    help="skip the single-net side measurements (Add tree, Mul, Fib(27))")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="batch line: skip the served measurements")
+    ap.add_argument("--serve-rates", default="1e4,1e5",
+                    help="batch line: served arrival rates (nets/s), comma-separated")
+    ap.add_argument("--serve-duration", type=float, default=10.0,
+                    help="batch line: seconds of arrivals per served rate")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay measurement")
     ap.add_argument("--pipeline", action="store_true",
                     help="time the paper's own evaluation loop (ablation) instead of the engine")
@@ -285,12 +371,23 @@ def main():
         sys.exit(2)
 
     par_baseline = None
-    if args.workload == "batch" and not args.no_cpu_baseline and not args.copy_calibration:
+    pool_ref = None  # (oracle record, per-net interaction counts) of the served pool
+    pool_nets = None
+    want_serve = args.workload == "serve" or (args.workload == "batch" and not args.no_serve)
+    if want_serve and not args.copy_calibration:
+        from paper_1404_0076_amd import nets as _nets
+        log(f"building the served pool ({args.pool} nets)")
+        pool_nets = _nets.config5_pool(seed=2, n_nets=args.pool)
+    if not args.no_cpu_baseline and not args.copy_calibration:
         # the oracle on all host cores, before the GPU is initialised
         from paper_1404_0076_amd import nets as _nets
-        log("cpu baseline (parallel)")
-        par_baseline = cpu_baseline_parallel(_nets.arith_rules(),
-                                             _nets.config4_batch(seed=args.seed, n_nets=args.n_nets))
+        if args.workload == "batch":
+            log("cpu baseline (parallel)")
+            par_baseline = cpu_baseline_parallel(_nets.arith_rules(),
+                                                 _nets.config4_batch(seed=args.seed, n_nets=args.n_nets))
+        if want_serve:
+            log("oracle over the served pool (parallel)")
+            pool_ref = oracle_parallel(_nets.arith_rules(), pool_nets, what="pool nets")
 
     import torch
 
@@ -313,7 +410,7 @@ def main():
     elif args.workload == "algae":
         R = nets.algae_rules()
     if args.workload == "serve":
-        return bench_serve(args, P, R, nets, torch)
+        return bench_serve(args, P, R, nets, torch, pool_ref, pool_nets)
     if args.workload == "batch":
         net_list = nets.config4_batch(seed=args.seed, n_nets=args.n_nets)
         workload = {"workload": f"batch of {args.n_nets} nets (Add tree / Mul / Fib mix, "
@@ -428,21 +525,33 @@ def main():
         out["graph"] = {"value": gtot * args.steps / gwall, "ms_per_step": gwall * 1e3 / args.steps}
     h.free()
     if args.workload == "batch" and not args.no_single:
-        # the plain single-net evaluator on the same GPU, for the comparison
-        single = nets.config2_mul(args.seed)
-        ua, un, st, it = size_batch(P, R, [single], 1024)
-        hs = P.batch_load(R, [single], agent_caps=ua + 64, name_caps=un + 64)
-        hs.set_config(wg_size=1024)
-        hs.reset(); hs.reduce_async(); torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(3):
-            hs.reset()
-            hs.reduce_async()
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t1) / 3
-        out["single_net"] = {"workload": f"Mul(S^{single.meta['a']} Z, S^{single.meta['b']} Z)",
-                             "value": float(it[0]) / dt, "ms": dt * 1000, "steps": int(st[0])}
-        hs.free()
+        # the plain single-net evaluator on the same GPU: the three single-net
+        # workloads (Add tree seed 0, Mul seed 0, Fib(27))
+        singles = {}
+        for key, net, what in (
+                ("addtree", nets.config1_add_tree(0), "balanced Add tree over 1024 numerals in [0,256), seed 0"),
+                ("mul", nets.config2_mul(0), None),
+                ("fib27", nets.config3_fib(27), "Fib(S^27 Z)")):
+            if what is None:
+                what = f"Mul(S^{net.meta['a']} Z, S^{net.meta['b']} Z), seed 0"
+            log(f"single net {key}")
+            rec = time_single(P, R, net)
+            rec["workload"] = what
+            singles[key] = rec
+        out["single_net_configs"] = singles
+        out["single_net"] = dict(singles["mul"])
+    if args.workload == "batch" and not args.no_serve:
+        pool, caps, inter_pool = served_pool(P, R, nets, args.pool, pool=pool_nets)
+        ref = inter_pool if pool_ref is None else pool_ref[1]
+        rates = [float(x) for x in args.serve_rates.split(",") if x]
+        out["served"] = {
+            "workload": f"Poisson arrivals from a pool of {len(pool)} nets (batch mix, seed 2), "
+                        f"native serving loop, {args.round_steps} steps per round",
+            "interactions_checked_against": "the sizing pass" if pool_ref is None else "the oracle",
+            "rates": [measure_served(P, R, pool, caps, ref, rate, args.serve_duration,
+                                     args.round_steps) for rate in rates]}
+        if pool_ref is not None:
+            out["served"]["cpu_baseline"] = pool_ref[0]
     if not args.no_cpu_baseline:
         ordered = [net_list[i] for i in order] if args.workload == "batch" else net_list
         log("cpu baseline")

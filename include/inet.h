@@ -298,22 +298,44 @@ int inet_server_stats(const inet_server *s, int64_t *free_bytes, int32_t *free_s
  * admitted for the next one.  A request that runs out of capacity is admitted
  * again with 8x its capacities (up to 4096x).  Per request the call writes its
  * completion time (seconds since the start), status, interaction count and
- * steps; the normal forms are not read back.  The server must be idle (no
- * admitted nets).  INET_ELIMIT when time_limit_s passes, INET_ENOMEM when a
- * request cannot be admitted into an empty server. */
+ * steps.  The server must be idle (no admitted nets).  INET_ELIMIT when
+ * time_limit_s passes, INET_ENOMEM when a request cannot be admitted into an
+ * empty server.
+ *
+ * `capture` (NULL: none) asks for more per request, all caller-owned host
+ * memory: per_rule[i * n_rules + r] = interactions of rule r of request i
+ * (copied back with the net states every round); and, for each request with
+ * want_nf[i] != 0, its canonical normal-form stream (as inet_readback writes
+ * it), read back when the request finishes, before its slot is reused.  The
+ * streams are written back to back into nf_buf (nf_cap int32 words) in
+ * completion order: request i's occupies nf_buf[nf_pos[i] .. nf_pos[i] +
+ * nf_len[i]).  Requests not flagged, or that failed, get nf_pos -1 and
+ * nf_len 0.  A stream that does not fit gets nf_pos -1 and nf_len its length,
+ * the run goes on, and the call returns INET_ERANGE at the end (all other
+ * outputs are written).  Reading streams back costs a device-to-host copy of
+ * the net's heap each, inside the loop: it is meant for checking, not for
+ * timing. */
 typedef struct {
   int64_t rounds;
   int32_t max_resident;
   int32_t retries;
   double wall_s;
 } inet_serve_stats;
+typedef struct {
+  uint64_t *per_rule;     /* [n_req][n_rules], or NULL */
+  const uint8_t *want_nf; /* [n_req], or NULL: no normal forms */
+  int32_t *nf_buf;        /* nf_cap words */
+  int64_t nf_cap;
+  int64_t *nf_pos;        /* [n_req] (required with want_nf) */
+  int64_t *nf_len;        /* [n_req] (required with want_nf) */
+} inet_serve_capture;
 int inet_server_run(inet_server *s, int32_t n_pool, const int32_t *label, const int32_t *port,
                     const int64_t *agent_off, const int32_t *eq_lhs, const int32_t *eq_rhs,
                     const int64_t *eq_off, const int32_t *n_names, const int64_t *agent_cap,
                     const int64_t *name_cap, int64_t n_req, const double *arrival_s,
                     const int32_t *pick, uint32_t round_steps, double time_limit_s,
                     hipStream_t stream, double *done_s, int32_t *status, uint64_t *interactions,
-                    uint32_t *steps, inet_serve_stats *stats);
+                    uint32_t *steps, inet_serve_stats *stats, const inet_serve_capture *capture);
 void inet_server_free(inet_server *s);
 
 #ifdef __cplusplus

@@ -93,7 +93,7 @@ def library():
             "inet_server_release": [_P, _I64], "inet_server_stats": [_P, _P, _P, _P],
             "inet_reduce_pipeline": [_P, _P, _U64],
             "inet_server_run": [_P, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _P, _P,
-                                ctypes.c_uint32, ctypes.c_double, _P, _P, _P, _P, _P, _P],
+                                ctypes.c_uint32, ctypes.c_double, _P, _P, _P, _P, _P, _P, _P],
         }
         for name, args in sig.items():
             f = getattr(lib, name)
@@ -375,6 +375,12 @@ class _ServeStats(ctypes.Structure):
                 ("retries", ctypes.c_int32), ("wall_s", ctypes.c_double)]
 
 
+class _ServeCapture(ctypes.Structure):
+    _fields_ = [("per_rule", ctypes.c_void_p), ("want_nf", ctypes.c_void_p),
+                ("nf_buf", ctypes.c_void_p), ("nf_cap", ctypes.c_int64),
+                ("nf_pos", ctypes.c_void_p), ("nf_len", ctypes.c_void_p)]
+
+
 class Server:
     """Continuous batching (inet_server_*): admit nets while others run."""
 
@@ -422,12 +428,16 @@ class Server:
         return int(t.value)
 
     def run(self, pool, arrivals, pick, caps=None, round_steps: int = 256,
-            time_limit: float = 600.0, stream=None) -> dict:
+            time_limit: float = 600.0, stream=None, per_rule: bool = False,
+            want_nf=None, nf_words: int = 1 << 24) -> dict:
         """The native serving loop (inet_server_run) over ``pool``: request i
         is ``pool[pick[i]]`` arriving ``arrivals[i]`` seconds after the start.
         ``caps[j] = (agent_cap, name_cap)`` or None for the defaults.  Returns
         per-request completion times, statuses, interaction counts and steps
-        plus the loop's statistics."""
+        plus the loop's statistics; with ``per_rule`` also the per-rule counts
+        of every request, and with ``want_nf`` (a boolean per request) the
+        normal-form streams of the flagged requests (``nf[i]``, None for the
+        others), read back within ``nf_words`` int32 words in all."""
         from .nets import pack
         s, _ = _stream_handle(stream)
         label, port, a_off, eql, eqr, e_off, n_names = pack(pool)
@@ -447,16 +457,35 @@ class Server:
         steps = np.zeros(n, np.uint32)
         st = _ServeStats()
         ptr = lambda a: None if a is None else a.ctypes.data  # noqa: E731
+        cap = None
+        nr = max(1, self.rules.n_rules)
+        pr = np.zeros((n, nr), np.uint64) if per_rule else None
+        wnf = nf_buf = nf_pos = nf_len = None
+        if want_nf is not None:
+            wnf = _arr(np.asarray(want_nf, dtype=bool).astype(np.uint8), np.uint8)
+            assert len(wnf) == n
+            nf_buf = np.zeros(max(1, nf_words), np.int32)
+            nf_pos = np.zeros(n, np.int64)
+            nf_len = np.zeros(n, np.int64)
+        if per_rule or want_nf is not None:
+            cap = _ServeCapture(ptr(pr), ptr(wnf), ptr(nf_buf), 0 if nf_buf is None else nf_buf.size,
+                                ptr(nf_pos), ptr(nf_len))
         rc = library().inet_server_run(
             self._h, len(pool), ptr(label), ptr(port), ptr(a_off), ptr(eql), ptr(eqr), ptr(e_off),
             ptr(n_names), ptr(ac), ptr(nc), n, ptr(arr), ptr(pk_), round_steps, time_limit, s,
             done.ctypes.data, status.ctypes.data, inter.ctypes.data, steps.ctypes.data,
-            ctypes.byref(st))
+            ctypes.byref(st), None if cap is None else ctypes.byref(cap))
         if rc:
             raise InetError(rc, "inet_server_run")
-        return {"done": done, "status": status, "interactions": inter, "steps": steps,
-                "rounds": int(st.rounds), "max_resident": int(st.max_resident),
-                "retries": int(st.retries), "wall": float(st.wall_s)}
+        out = {"done": done, "status": status, "interactions": inter, "steps": steps,
+               "rounds": int(st.rounds), "max_resident": int(st.max_resident),
+               "retries": int(st.retries), "wall": float(st.wall_s)}
+        if per_rule:
+            out["per_rule"] = pr[:, : self.rules.n_rules]
+        if want_nf is not None:
+            out["nf"] = [nf_buf[nf_pos[i]: nf_pos[i] + nf_len[i]].copy() if nf_pos[i] >= 0 else None
+                         for i in range(n)]
+        return out
 
     def step(self, max_steps: int, stream=None):
         s, _ = _stream_handle(stream)

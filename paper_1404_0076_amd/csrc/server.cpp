@@ -98,12 +98,6 @@ void give_range(inet_server *s, size_t off, size_t len) {
   }
 }
 
-// the engine width of a round: the library default unless the caller chose
-// one (a round runs every resident net for a bounded number of steps, so a
-// wide frontier must not lengthen it: the default engines handle wide
-// frontiers with all their waves)
-inet_config serving_config(inet_config cfg) { return cfg; }
-
 inet_server::Slot *slot_of(inet_server *s, int64_t ticket) {
   auto it = s->by_ticket.find(ticket);
   if (it == s->by_ticket.end()) return nullptr;
@@ -248,7 +242,7 @@ int inet_server_step(inet_server *s, hipStream_t stream, uint32_t max_steps) {
   const int n = (int)s->running.size();
   s->order_host = s->running;
   HIPCHK(hipMemcpyAsync(s->d_order, s->order_host.data(), 4 * (size_t)n, hipMemcpyHostToDevice, stream));
-  const inet_config cfg = serving_config(s->cfg);
+  const inet_config &cfg = s->cfg;
   const LaunchShape sh = effective_shape(cfg, n > 1 ? n : 2, s->rules);
   int grid = 1;
   int rc = resident_grid(sh, s->rules, cfg, n, &grid);
@@ -374,10 +368,15 @@ int inet_server_run(inet_server *s, int32_t n_pool, const int32_t *label, const 
                     const int64_t *name_cap, int64_t n_req, const double *arrival_s,
                     const int32_t *pick, uint32_t round_steps, double time_limit_s,
                     hipStream_t stream, double *done_s, int32_t *status, uint64_t *interactions,
-                    uint32_t *steps, inet_serve_stats *stats) {
+                    uint32_t *steps, inet_serve_stats *stats, const inet_serve_capture *capture) {
   if (!s || n_pool <= 0 || n_req < 0 || !agent_off || !eq_off || !n_names || round_steps == 0)
     return INET_EINVAL;
   if (n_req > 0 && (!arrival_s || !pick || !done_s || !status || !interactions || !steps))
+    return INET_EINVAL;
+  const bool want_rules = capture && capture->per_rule;
+  const bool want_nf = capture && capture->want_nf;
+  if (want_nf && (!capture->nf_pos || !capture->nf_len || capture->nf_cap < 0 ||
+                  (capture->nf_cap > 0 && !capture->nf_buf)))
     return INET_EINVAL;
   if (!s->running.empty() || !s->finished.empty() || s->round_in_flight) return INET_EINVAL;
   const CompiledRules &R = s->rules;
@@ -388,7 +387,8 @@ int inet_server_run(inet_server *s, int32_t n_pool, const int32_t *label, const 
     if (pick[i] < 0 || pick[i] >= n_pool) return INET_EINVAL;
     if (i && arrival_s[i] < arrival_s[i - 1]) return INET_EINVAL;
   }
-  // validate the pool once
+  // validate the pool once (the interfaces are kept when normal forms are read back)
+  std::vector<std::vector<int32_t>> pool_iface(want_nf ? n_pool : 0);
   for (int32_t j = 0; j < n_pool; j++) {
     const int64_t a0 = agent_off[j], na = agent_off[j + 1] - a0;
     const int64_t e0 = eq_off[j], ne = eq_off[j + 1] - e0;
@@ -397,7 +397,17 @@ int inet_server_run(inet_server *s, int32_t n_pool, const int32_t *label, const 
     int rc = validate_net(R, label + a0, port + 2 * a0, na, eq_lhs + e0, eq_rhs + e0, ne,
                           n_names[j], &iface);
     if (rc) return rc;
+    if (want_nf) pool_iface[j].swap(iface);
   }
+  if (want_rules && R.nr > 0)
+    std::memset(capture->per_rule, 0, sizeof(uint64_t) * (size_t)n_req * (size_t)R.nr);
+  if (want_nf)
+    for (int64_t i = 0; i < n_req; i++) {
+      capture->nf_pos[i] = -1;
+      capture->nf_len[i] = 0;
+    }
+  int64_t nf_used = 0;
+  bool nf_short = false;
   // the pool's initial images and the admission records stay resident for the run
   const int32_t M = s->max_slots;
   const size_t img_bytes = al(4 * (size_t)A + 4) + al(8 * (size_t)A + 8) + al(8 * (size_t)E + 8) +
@@ -413,6 +423,7 @@ int inet_server_run(inet_server *s, int32_t n_pool, const int32_t *label, const 
   AdmitRec *h_admit = nullptr;
   int32_t *h_order = nullptr;
   NetState *h_states = nullptr;
+  unsigned long long *h_rules = nullptr;  // per-rule counts of every slot (capture only)
   int rc = INET_OK;
   {
     std::vector<int32_t> eqs((size_t)2 * E + 2);
@@ -427,6 +438,8 @@ int inet_server_run(inet_server *s, int32_t n_pool, const int32_t *label, const 
     if (e == hipSuccess) e = hipHostMalloc((void **)&h_admit, sizeof(AdmitRec) * (size_t)M * 2);
     if (e == hipSuccess) e = hipHostMalloc((void **)&h_order, 4 * (size_t)M);
     if (e == hipSuccess) e = hipHostMalloc((void **)&h_states, sizeof(NetState) * (size_t)M);
+    if (e == hipSuccess && want_rules && R.nr > 0)
+      e = hipHostMalloc((void **)&h_rules, 8 * (size_t)R.nr * (size_t)M);
     if (e != hipSuccess) rc = INET_EHIP;
   }
   std::vector<int64_t> req_of(M, -1);
@@ -546,7 +559,7 @@ int inet_server_run(inet_server *s, int32_t n_pool, const int32_t *label, const 
     s->order_host = s->running;
     if (hipMemcpyAsync(s->d_order, h_order, 4 * (size_t)n, hipMemcpyHostToDevice, stream) !=
         hipSuccess) { rc = INET_EHIP; break; }
-    const inet_config cfg = serving_config(s->cfg);
+    const inet_config &cfg = s->cfg;
     const LaunchShape sh = effective_shape(cfg, n > 1 ? n : 2, R);
     int grid = 1;
     rc = resident_grid(sh, R, cfg, n, &grid);
@@ -556,6 +569,11 @@ int inet_server_run(inet_server *s, int32_t n_pool, const int32_t *label, const 
     if (rc) break;
     if (hipMemcpyAsync(h_states, s->d_states, sizeof(NetState) * (size_t)M, hipMemcpyDeviceToHost,
                        stream) != hipSuccess) { rc = INET_EHIP; break; }
+    if (h_rules && hipMemcpyAsync(h_rules, s->d_per_rule, 8 * (size_t)nr * (size_t)M,
+                                  hipMemcpyDeviceToHost, stream) != hipSuccess) {
+      rc = INET_EHIP;
+      break;
+    }
     rounds++;
     max_res = std::max(max_res, n);
     // requests arriving during the round are admitted for the next one
@@ -575,8 +593,8 @@ int inet_server_run(inet_server *s, int32_t n_pool, const int32_t *label, const 
       }
       const int64_t req = req_of[si];
       const int32_t boost = boost_of[si];
-      release(si);
       if (st.status == ST_ENOMEM && boost < 4096) {
+        release(si);
         retry.emplace_back(req, boost * 8);
         retries++;
         continue;
@@ -585,7 +603,25 @@ int inet_server_run(inet_server *s, int32_t n_pool, const int32_t *label, const 
       status[req] = st.status;
       interactions[req] = st.interactions;
       steps[req] = st.steps;
+      if (h_rules)
+        std::memcpy(capture->per_rule + (size_t)req * nr, h_rules + (size_t)si * nr, 8 * (size_t)nr);
+      if (want_nf && capture->want_nf[req] && st.status >= 0) {
+        // the heap is still the slot's: nothing is installed there before the next round
+        std::vector<int32_t> nf;
+        const int brc = readback_net(R, s->slots[si].desc, st, pool_iface[pick[req]], &nf);
+        if (brc) { rc = brc; break; }
+        capture->nf_len[req] = (int64_t)nf.size();
+        if (nf_used + (int64_t)nf.size() <= capture->nf_cap) {
+          if (!nf.empty()) std::memcpy(capture->nf_buf + nf_used, nf.data(), 4 * nf.size());
+          capture->nf_pos[req] = nf_used;
+          nf_used += (int64_t)nf.size();
+        } else {
+          nf_short = true;
+        }
+      }
+      release(si);
     }
+    if (rc != INET_OK) break;
     s->running.swap(still);
   }
   if (rc != INET_OK) {
@@ -597,6 +633,7 @@ int inet_server_run(inet_server *s, int32_t n_pool, const int32_t *label, const 
   if (h_admit) (void)hipHostFree(h_admit);
   if (h_order) (void)hipHostFree(h_order);
   if (h_states) (void)hipHostFree(h_states);
+  if (h_rules) (void)hipHostFree(h_rules);
   give_range(s, img_off, img_bytes);
   if (stats) {
     stats->rounds = rounds;
@@ -604,6 +641,7 @@ int inet_server_run(inet_server *s, int32_t n_pool, const int32_t *label, const 
     stats->retries = (int32_t)retries;
     stats->wall_s = now();
   }
+  if (rc == INET_OK && nf_short) rc = INET_ERANGE;
   return rc;
 }
 

@@ -131,17 +131,22 @@ def serve(rules, pool: Sequence, arrivals: np.ndarray, pick: Sequence[int],
 def serve_native(rules, pool: Sequence, arrivals: np.ndarray, pick: Sequence[int],
                  caps: Optional[Sequence] = None, max_slots: int = 4096,
                  workspace_bytes: int = 8 << 30, round_steps: int = 256, wg_size: int = 0,
-                 time_limit: float = 600.0, server: Optional[Server] = None) -> ServeReport:
-    """The serving loop of ``serve`` run by the library (inet_server_run);
-    results carry counters only (no normal forms)."""
+                 time_limit: float = 600.0, server: Optional[Server] = None,
+                 per_rule: bool = False, want_nf=None) -> ServeReport:
+    """The serving loop of ``serve`` run by the library (inet_server_run).
+    Results carry counters; with ``per_rule`` also the per-rule counts, and
+    the normal forms of the requests flagged in ``want_nf``."""
     import torch
 
     srv = server or Server(rules, max_slots, workspace_bytes)
     srv.set_config(wg_size=wg_size)
     out = srv.run(pool, arrivals, pick, caps=caps, round_steps=round_steps,
-                  time_limit=time_limit, stream=torch.cuda.current_stream())
+                  time_limit=time_limit, stream=torch.cuda.current_stream(), per_rule=per_rule,
+                  want_nf=want_nf)
     served = [Served(int(pick[i]), float(arrivals[i]), float(out["done"][i]), int(out["status"][i]),
-                     int(out["interactions"][i]), int(out["steps"][i]))
+                     int(out["interactions"][i]), int(out["steps"][i]),
+                     out["nf"][i] if want_nf is not None else None,
+                     out["per_rule"][i] if per_rule else None)
               for i in range(len(pick))]
     if server is None:
         srv.free()
