@@ -94,7 +94,10 @@ typedef enum {
   INET_EAGAIN = -5,  /* server: no free slot or memory; retry later         */
   INET_EHIP = -6,    /* a HIP runtime call failed                            */
   INET_ENOSYS = -7,  /* not supported on this device / build                */
-  INET_EINTERNAL = -8 /* an invariant of the evaluator was violated          */
+  INET_EINTERNAL = -8, /* an invariant of the evaluator was violated         */
+  INET_ETIMEDOUT = -9  /* a workgroup of the multi-workgroup engine waited at
+                          a barrier longer than the configured give-up without
+                          progress (the net's state is then unusable)        */
 } inet_status;
 
 typedef struct {
@@ -136,6 +139,26 @@ typedef struct {
                                reserves its agents, name cells and frontier
                                entries with atomics of its own (all waves
                                step together, at every frontier width)    */
+  int32_t solo_max;         /* engine 3, wider engines: wave 0 steps alone
+                               while at most this many pairs are active
+                               (0: 64)                                     */
+  int32_t grid;             /* a handle holding one net, engine 3: 0 the
+                               multi-workgroup engine over every workgroup
+                               that can be resident; > 0 over at most this
+                               many; -1 one workgroup only.  Workgroup 0
+                               steps the net alone while at most grid_hi
+                               pairs are active; above that the steps are
+                               shared by ceil(active / grid_ppw) workgroups
+                               until at most grid_lo are left               */
+  int32_t grid_lo;          /* 0: 1024 */
+  int32_t grid_hi;          /* 0: 2048 (at least grid_lo) */
+  int32_t grid_ppw;         /* 0: the engine width */
+  int32_t timeout_us;       /* multi-workgroup engine and pointer jumping of
+                               one net: a workgroup waiting at a barrier gives
+                               up after this many microseconds without
+                               progress of the others (INET_ETIMEDOUT for the
+                               engine; the jumping pass just ends early);
+                               0: 2 s                                        */
 } inet_config;
 
 typedef struct inet_net inet_net;
@@ -206,6 +229,13 @@ int inet_readback(inet_net *h, int32_t net, int32_t *buf, int64_t cap, int64_t *
 /* Per-rule interaction counts of net i (cap >= n_rules words). */
 int inet_per_rule(inet_net *h, int32_t net, uint64_t *counts, int32_t cap);
 
+/* The raw name cells of a finished net (a diagnostic of the pointer-jumping
+ * pass): cell x (0 <= x < names_used) holds EMPTY (0x7fffffff) while no
+ * occurrence of name x has been extracted to the top of an equation, else
+ * the term parked there (>= 0 an agent, < 0 the name -1 - value).  Needs
+ * inet_results first; cap too small: INET_ERANGE with *len set. */
+int inet_cells(inet_net *h, int32_t net, int32_t *buf, int64_t cap, int64_t *len);
+
 /* Algorithmic bytes one interaction of each rule moves in the evaluator's
  * layout (cap >= n_rules words): 8 (the pair) + 4 (label + ports) of both
  * agents + 4 (label + ports) of each new agent + 4 per fresh name cell + 8 per
@@ -221,10 +251,12 @@ int inet_rules_check(const inet_rules *rules, int32_t *n_new, int32_t *n_fresh, 
                      int32_t *bytes, int32_t cap);
 
 /* Host only: build the engines specialised for this rule table (engines 3
- * and 4) for the given device architecture (e.g. "gfx950") with the run-time
- * compiler, without a device; *code_bytes gets the total size of the two code
- * objects, log (may be NULL) the compiler's messages.  INET_ENOSYS if the
- * compiler fails. */
+ * and 4, 1024 lanes; engine 3 with its multi-workgroup engine) for the given
+ * device architecture (e.g. "gfx950") with the run-time compiler, without a
+ * device; *code_bytes gets the total size of the two code objects, log (may be
+ * NULL) the compiler's messages.  INET_ENOSYS if the compiler fails.  On a
+ * device the same code objects are built on first use, one per rule table,
+ * engine and engine width. */
 int inet_jit_build(const inet_rules *rules, const char *arch, size_t *code_bytes, char *log,
                    size_t log_cap);
 
@@ -251,6 +283,30 @@ float inet_last_kernel_ms(inet_net *h);
  * resumed.  Unlike every other entry point it allocates temporary device
  * memory (hipMalloc) for its equation lists. */
 int inet_reduce_pipeline(inet_net *h, hipStream_t stream, uint64_t max_iterations);
+
+/* The ablation's device primitives (Sections 3.4-3.5: the scan of the
+ * allocation, the removal of dummies, the sort of the equations by variable
+ * and the merge of communication-eligible neighbours), on caller device
+ * arrays.  Each allocates temporary device memory, runs on `stream` and
+ * synchronises it before returning.
+ *   inet_prim_scan: out[i] = in[0] + ... + in[i] (uint64, wrapping).
+ *   inet_prim_select: the elements of in that differ from `drop`, in their
+ *     order, into out; *n_out (host) gets their number.
+ *   inet_prim_sort_pairs: (key, value) pairs sorted by key ascending, stably,
+ *     in place.
+ *   inet_prim_reduce_by_key: each run of equal adjacent keys becomes one
+ *     (key, value), the run's values folded left to right with op: 0 sum
+ *     (the example of Section 3.5), 1 the merge of two equations sharing a
+ *     variable, (x, t) and (x, s) give (s, t), an equation packed as
+ *     lhs | rhs << 32; *n_out (host) gets the number of runs.
+ * n < 0, null pointers with n > 0, or an unknown op: INET_EINVAL. */
+int inet_prim_scan(const uint64_t *d_in, uint64_t *d_out, int64_t n, hipStream_t stream);
+int inet_prim_select(const uint64_t *d_in, uint64_t *d_out, int64_t n, uint64_t drop,
+                     int64_t *n_out, hipStream_t stream);
+int inet_prim_sort_pairs(uint32_t *d_keys, uint64_t *d_vals, int64_t n, hipStream_t stream);
+int inet_prim_reduce_by_key(const uint32_t *d_keys, const uint64_t *d_vals, int64_t n,
+                            uint32_t *d_keys_out, uint64_t *d_vals_out, int32_t op,
+                            int64_t *n_out, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Continuous batching (serving).  A server owns one caller-provided device

@@ -20,6 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libinet.so")
 
 OK, STUCK, EINVAL, ENOMEM, ELIMIT, ERANGE, EAGAIN, EHIP, ENOSYS, EINTERNAL = 0, 1, -1, -2, -3, -4, -5, -6, -7, -8
+ETIMEDOUT = -9
 
 EXPORTS = [
     "inet_workspace_bytes", "inet_load", "inet_batch_load", "inet_set_config", "inet_get_config",
@@ -29,7 +30,8 @@ EXPORTS = [
     "inet_graph_launch", "inet_server_create", "inet_server_set_config", "inet_server_net_bytes",
     "inet_server_submit", "inet_server_step", "inet_server_poll", "inet_server_result",
     "inet_server_per_rule", "inet_server_release", "inet_server_stats", "inet_server_free",
-    "inet_jit_build", "inet_server_run", "inet_reduce_pipeline",
+    "inet_jit_build", "inet_server_run", "inet_reduce_pipeline", "inet_cells",
+    "inet_prim_scan", "inet_prim_select", "inet_prim_sort_pairs", "inet_prim_reduce_by_key",
 ]
 
 
@@ -54,7 +56,23 @@ class _Result(ctypes.Structure):
 
 class _Config(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("jump", ctypes.c_int32),
-                ("max_resident", ctypes.c_int32), ("engine", ctypes.c_int32)]
+                ("max_resident", ctypes.c_int32), ("engine", ctypes.c_int32),
+                ("solo_max", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("grid_lo", ctypes.c_int32), ("grid_hi", ctypes.c_int32),
+                ("grid_ppw", ctypes.c_int32), ("timeout_us", ctypes.c_int32)]
+
+
+# tunables of inet_config beyond wg_size / jump / max_resident / engine (all
+# 0 = the library's default; grid -1 keeps a single net on one workgroup)
+CONFIG_KEYS = ("solo_max", "grid", "grid_lo", "grid_hi", "grid_ppw", "timeout_us")
+
+
+def _config(wg_size, jump, max_resident, engine, extra) -> "_Config":
+    bad = set(extra) - set(CONFIG_KEYS)
+    if bad:
+        raise TypeError(f"unknown configuration keys {sorted(bad)}")
+    return _Config(wg_size, 1 if jump else 0, max_resident, engine,
+                   *[int(extra.get(k, 0)) for k in CONFIG_KEYS])
 
 
 _lib = None
@@ -78,6 +96,10 @@ def library():
             "inet_reduce_async": [_P, _P, _U64], "inet_results": [_P, _P, _P],
             "inet_reduce": [_P, _P, _U64, _P], "inet_reset": [_P, _P],
             "inet_readback": [_P, _I32, _P, _I64, _P], "inet_per_rule": [_P, _I32, _P, _I32],
+            "inet_cells": [_P, _I32, _P, _I64, _P],
+            "inet_prim_scan": [_P, _P, _I64, _P], "inet_prim_select": [_P, _P, _I64, _U64, _P, _P],
+            "inet_prim_sort_pairs": [_P, _P, _I64, _P],
+            "inet_prim_reduce_by_key": [_P, _P, _I64, _P, _P, _I32, _P, _P],
             "inet_rule_bytes": [_P, _P, _I32], "inet_num_nets": [_P],
             "inet_rules_check": [_P, _P, _P, _P, _P, _I32],
             "inet_jit_build": [_P, ctypes.c_char_p, _P, _P, ctypes.c_size_t],
@@ -211,15 +233,30 @@ class Handle:
         return rc
 
     def set_config(self, wg_size: int = 0, jump: bool = True, max_resident: int = 0,
-                   engine: int = 0):
-        cfg = _Config(wg_size, 1 if jump else 0, max_resident, engine)
+                   engine: int = 0, **extra):
+        """Launch shape and tunables (inet_config); ``extra`` takes the keys
+        of CONFIG_KEYS."""
+        cfg = _config(wg_size, jump, max_resident, engine, extra)
         self._check(library().inet_set_config(self._h, ctypes.byref(cfg)), "inet_set_config")
 
     def get_config(self) -> dict:
         cfg = _Config()
         self._check(library().inet_get_config(self._h, ctypes.byref(cfg)), "inet_get_config")
-        return {"wg_size": cfg.wg_size, "jump": bool(cfg.jump), "max_resident": cfg.max_resident,
-                "engine": cfg.engine}
+        out = {"wg_size": cfg.wg_size, "jump": bool(cfg.jump), "max_resident": cfg.max_resident,
+               "engine": cfg.engine}
+        out.update({k: getattr(cfg, k) for k in CONFIG_KEYS})
+        return out
+
+    def cells(self, net: int = 0) -> np.ndarray:
+        """The raw name cells of a finished net (inet_cells), after results()."""
+        n = ctypes.c_int64(0)
+        rc = library().inet_cells(self._h, net, None, 0, ctypes.byref(n))
+        if rc not in (OK, ERANGE):
+            raise InetError(rc, "inet_cells")
+        buf = np.zeros(max(1, n.value), np.int32)
+        self._check(library().inet_cells(self._h, net, buf.ctypes.data, buf.size, ctypes.byref(n)),
+                    "inet_cells")
+        return buf[: n.value]
 
     def set_order(self, order: Sequence[int]):
         o = _arr(order, np.int32)
@@ -344,14 +381,15 @@ def load(rules, net: "nets.Net", agent_cap: int = 0, name_cap: int = 0, stream=N
 
 
 def reduce_net(rules, net, agent_cap: int = 0, name_cap: int = 0, wg_size: int = 0,
-               max_retries: int = 6, jump: bool = True, engine: int = 0):
+               max_retries: int = 6, jump: bool = True, engine: int = 0, **extra):
     """Load, reduce and read back one net; on ENOMEM reload with 4x capacity.
+    ``extra``: further configuration keys (CONFIG_KEYS).
     Returns (Result, normal-form stream, per-rule counts)."""
     agent_cap = agent_cap or max(4 * net.n_agents + 4096, 1 << 16)
     name_cap = name_cap or 4 * agent_cap
     for _ in range(max_retries):
         h = load(rules, net, agent_cap=agent_cap, name_cap=name_cap)
-        h.set_config(wg_size=wg_size, jump=jump, engine=engine)
+        h.set_config(wg_size=wg_size, jump=jump, engine=engine, **extra)
         res = h.reduce()[0]
         if res.status == ENOMEM:
             h.free()
@@ -398,8 +436,8 @@ class Server:
         self.max_slots = max_slots
 
     def set_config(self, wg_size: int = 0, jump: bool = True, max_resident: int = 0,
-                   engine: int = 0):
-        cfg = _Config(wg_size, 1 if jump else 0, max_resident, engine)
+                   engine: int = 0, **extra):
+        cfg = _config(wg_size, jump, max_resident, engine, extra)
         rc = library().inet_server_set_config(self._h, ctypes.byref(cfg))
         if rc:
             raise InetError(rc, "inet_server_set_config")
@@ -551,6 +589,69 @@ class Server:
             self.free()
         except Exception:
             pass
+
+
+class prim:
+    """The ablation's device primitives (inet_prim_*) on torch device tensors:
+    argument marshalling only."""
+
+    @staticmethod
+    def _ptr(t, dtype):
+        import torch
+        assert t.is_cuda and t.dtype == dtype and t.is_contiguous()
+        return ctypes.c_void_p(t.data_ptr())
+
+    @staticmethod
+    def scan(x):
+        """Inclusive prefix sum of an int64 tensor (as uint64, wrapping)."""
+        import torch
+        out = torch.empty_like(x)
+        s, _ = _stream_handle(None)
+        rc = library().inet_prim_scan(prim._ptr(x, torch.int64), prim._ptr(out, torch.int64),
+                                      x.numel(), s)
+        if rc:
+            raise InetError(rc, "inet_prim_scan")
+        return out
+
+    @staticmethod
+    def select(x, drop: int):
+        """The elements of an int64 tensor that differ from ``drop`` (as
+        uint64), in order."""
+        import torch
+        out = torch.empty_like(x)
+        n = ctypes.c_int64(0)
+        s, _ = _stream_handle(None)
+        rc = library().inet_prim_select(prim._ptr(x, torch.int64), prim._ptr(out, torch.int64),
+                                        x.numel(), int(drop) & ((1 << 64) - 1), ctypes.byref(n), s)
+        if rc:
+            raise InetError(rc, "inet_prim_select")
+        return out[: n.value]
+
+    @staticmethod
+    def sort_pairs(keys, vals):
+        """Stable sort of (int32 key as uint32, int64 value) pairs by key, in place."""
+        import torch
+        s, _ = _stream_handle(None)
+        rc = library().inet_prim_sort_pairs(prim._ptr(keys, torch.int32), prim._ptr(vals, torch.int64),
+                                            keys.numel(), s)
+        if rc:
+            raise InetError(rc, "inet_prim_sort_pairs")
+
+    @staticmethod
+    def reduce_by_key(keys, vals, op: int = 0):
+        """Runs of equal adjacent keys folded (op 0: sum; 1: the merge of two
+        equations sharing a variable).  Returns (keys, values) of the runs."""
+        import torch
+        ko = torch.empty_like(keys)
+        vo = torch.empty_like(vals)
+        n = ctypes.c_int64(0)
+        s, _ = _stream_handle(None)
+        rc = library().inet_prim_reduce_by_key(prim._ptr(keys, torch.int32), prim._ptr(vals, torch.int64),
+                                               keys.numel(), prim._ptr(ko, torch.int32),
+                                               prim._ptr(vo, torch.int64), op, ctypes.byref(n), s)
+        if rc:
+            raise InetError(rc, "inet_prim_reduce_by_key")
+        return ko[: n.value], vo[: n.value]
 
 
 def check_exports() -> List[str]:

@@ -127,8 +127,23 @@ __device__ __forceinline__ void wave_push(bool prod, int u, int v, Pair *lds_q, 
   }
 }
 
+// name-cell exchange: relaxed, at agent scope, so that it is also atomic
+// against the workgroups of a multi-workgroup engine (on gfx950 a relaxed
+// exchange is the same instruction at workgroup and agent scope: atomics are
+// performed at the L2)
 __device__ __forceinline__ int xchg(gint *p, int v) {
-  return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// device-scope (agent) counters of a multi-workgroup engine
+__device__ __forceinline__ int gadd(int *p, int v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int gload(const int *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gstore(int *p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // com: resolve the equation u = v.  Returns true with (ou, ov) when it ends
@@ -177,24 +192,6 @@ __device__ __forceinline__ int resolve_u(int op, int a, int b, int pa0, int pa1,
     return my_a + (idx - 2);
   }
   return -1 - (my_n + idx);
-}
-
-// pointer jumping over the cells [lo, hi) with stride: a cell whose value is
-// a name whose own cell is filled takes that cell's value (a com step)
-__device__ __forceinline__ void jump_cells(gint *__restrict__ bind, int lo, int hi, int stride) {
-  for (int x = lo; x < hi; x += stride) {
-    int v = bind[x];
-    int hops = 0;
-    while (v < 0 && hops < 64) {
-      const int y = ~v;
-      if (y == x) break;
-      const int w = bind[y];
-      if (w == EMPTY) break;
-      v = w;
-      hops++;
-    }
-    if (hops) bind[x] = v;
-  }
 }
 
 // one pass of the interaction phase with the rule template interpreted per
@@ -489,13 +486,17 @@ __device__ __forceinline__ int opaque(int v) {
   return v;
 }
 
-// the engine's counters: LDS words shared by the waves of the workgroup, or
-// wave-uniform registers when the engine is one wave
-template <bool SOLO>
+// the engine's counters: wave-uniform registers when the engine is one wave
+// (CM_REG), LDS words shared by the waves of the workgroup (CM_LDS), or, in a
+// step shared by several workgroups (CM_GRID), the net's heap tops, residual
+// count and status in global memory at agent scope with the new active pairs
+// staged in the workgroup's LDS tile
+enum { CM_REG = 0, CM_LDS = 1, CM_GRID = 2 };
+template <int CM>
 struct Ctr;
 
 template <>
-struct Ctr<true> {
+struct Ctr<CM_REG> {
   int agent_top, name_top, next, nstuck, err;
   __device__ __forceinline__ int agents(int n, int, int) {
     const int b = agent_top;
@@ -525,7 +526,7 @@ struct Ctr<true> {
 };
 
 template <>
-struct Ctr<false> {
+struct Ctr<CM_LDS> {
   int *agent_top, *name_top, *next, *nstuck, *status;
   __device__ __forceinline__ int take(int *p, int n, int lane, int lead) {
     int b = 0;
@@ -550,6 +551,42 @@ struct Ctr<false> {
   __device__ __forceinline__ void fail(bool nomem, bool internal) {
     if (internal) *status = ST_EINTERNAL;
     else if (nomem) *status = ST_ENOMEM;
+  }
+};
+
+template <>
+struct Ctr<CM_GRID> {
+  int *agent_top, *name_top, *nstuck, *status;  // global (the net's state)
+  int *next;                                    // LDS: entries in the tile
+  int *spill_next;                              // global: entries of the next frontier
+  __device__ __forceinline__ int take(int *p, int n) {
+    int b = 0;
+    if (__lane_id() == 0) b = gadd(p, n);
+    return __builtin_amdgcn_readfirstlane(b);
+  }
+  __device__ __forceinline__ int append(int n) {
+    int b = 0;
+    if (__lane_id() == 0) b = atomicAdd(next, n);
+    return __builtin_amdgcn_readfirstlane(b);
+  }
+  // n entries past the LDS tile, straight into the global next frontier
+  __device__ __forceinline__ int spill(int n) { return take(spill_next, n); }
+  __device__ __forceinline__ int stuck(int n) { return take(nstuck, n); }
+  __device__ __forceinline__ void agents_names(int na, int nn, int &ba, int &bn) {
+    int a = 0, b = 0;
+    if (__lane_id() == 0) {
+      if (na) a = gadd(agent_top, na);
+      if (nn) b = gadd(name_top, nn);
+    }
+    ba = __builtin_amdgcn_readfirstlane(a);
+    bn = __builtin_amdgcn_readfirstlane(b);
+  }
+  __device__ __forceinline__ void fail_uniform(int lane, int lead) {
+    if (lane == lead) gstore(status, ST_ENOMEM);
+  }
+  __device__ __forceinline__ void fail(bool nomem, bool internal) {
+    if (internal) gstore(status, ST_EINTERNAL);
+    else if (nomem) gstore(status, ST_ENOMEM);
   }
 };
 
@@ -693,13 +730,14 @@ __device__ __forceinline__ void decide_links(const Lane &L, gint *bind, unsigned
 // group of a wave ranked by mask counts
 // HOLD (one-wave steps): the lane keeps its first new active pair in
 // registers (ha, hb; ha < 0 if none) and appends only the others
-template <int QCAP, int MAXL, bool SOLO, bool LANE, bool HOLD = false>
+template <int QCAP, int MAXL, int CM, bool LANE, bool HOLD = false>
 __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, int lb, int pa0,
                                             int pa1, int pb0, int pb1, const NetDesc &D,
                                             gint *agent, gint *bind,
                                             gint2 *stuck, const int *rule_of, Pair *nq_l,
-                                            gint2 *nq_g, Ctr<SOLO> &C, int &loops_lane,
+                                            gint2 *nq_g, Ctr<CM> &C, int &loops_lane,
                                             unsigned &rc_lane, int &ha, int &hb) {
+  constexpr bool SOLO = CM == CM_REG;
   const int lane = __lane_id();
   const int code = rule_of[valid ? la * rt::NS + lb : 0];
   // take the loaded ports through a copy on every path: later rule blocks then
@@ -875,12 +913,20 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
         }
       }
     } else {
+      // entries past the LDS tile go to the global queue: at the same index
+      // when one workgroup owns the net, else at a range of the shared next
+      // frontier reserved for this wave's overflow
+      int gofs = 0;
+      if constexpr (CM == CM_GRID) {
+        const int first = base > QCAP ? base : QCAP;
+        gofs = C.spill(base + tot - first) - first;
+      }
 #pragma unroll
       for (int j = 0; j < MAXL; j++) {
         if (pu[j] >= 0) {
           const int i = base + count_below(m[j]);
           if (i < QCAP) nq_l[i] = mkpair(pu[j], pv[j]);
-          else if (i < D.qcap) *at2(nq_g, (unsigned)i) = pk(pu[j], pv[j]);
+          else if (i + gofs < D.qcap) *at2(nq_g, (unsigned)(i + gofs)) = pk(pu[j], pv[j]);
           else lane_err = true;
         }
         base += __popcll(m[j]);
@@ -921,350 +967,712 @@ __device__ __forceinline__ void fetch_pair(int base, int n, int tid, const Pair 
 }
 #endif  // INET_STATIC_RULES
 
+// Pointer jumping (com along name chains, Section 3.6): a cell x that holds a
+// name y whose own cell holds a term t takes t (x = y and y = t give x = t).
+// One hop per cell and round; applied to every cell in rounds separated by
+// barriers, this at least halves every chain per round, so a chain of L names
+// is one hop after ceil(log2 L) rounds.  A hop that would make a cell hold its
+// own name is skipped (it would only close a vicious circle, whose cells are
+// reachable from no agent and no interface name).
+__device__ __forceinline__ bool jump_hop(gint *__restrict__ bind, int x) {
+  const int v = bind[x];
+  if (v >= 0) return false;  // an agent, or EMPTY
+  const int y = ~v;
+  if (y == x) return false;
+  const int w = bind[y];
+  if (w == EMPTY || w == ~x || w == v) return false;
+  bind[x] = w;
+  return true;
+}
+
+// wait until the epoch counter moves past `seen`; false on give-up after
+// `timeout` wall-clock ticks without progress (no new epoch and no change of
+// the heartbeat word).  Polls back off from tens of nanoseconds to
+// microseconds the longer the wait lasts.
+__device__ __forceinline__ bool wait_epoch(GridCtl *ctl, int seen, unsigned long long timeout) {
+  unsigned long long t0 = wall_clock64();
+  int hb = gload(&ctl->heartbeat);
+  for (int polls = 0;; polls++) {
+    if (gload(&ctl->gen) != seen) return true;
+    const int h = gload(&ctl->heartbeat);
+    const unsigned long long t = wall_clock64();
+    if (h != hb) {
+      hb = h;
+      t0 = t;
+    } else if (t - t0 > timeout) {
+      return false;
+    }
+    if (polls < 256) __builtin_amdgcn_s_sleep(1);
+    else if (polls < 4096) __builtin_amdgcn_s_sleep(32);
+    else __builtin_amdgcn_s_sleep(127);
+  }
+}
+
+// barrier over all G workgroups of a launch (every workgroup arrives); thread
+// 0 of each workgroup holds `seen`, the epoch it last saw.  `last` runs in the
+// last arriving workgroup before the others are released.  False on give-up.
+template <class F>
+__device__ __forceinline__ bool grid_sync(GridCtl *ctl, int G, int &seen, unsigned long long timeout,
+                                          F &&last) {
+  bool ok = true;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (gadd(&ctl->arrive, 1) == G - 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      last();
+      gstore(&ctl->arrive, 0);
+      __hip_atomic_store(&ctl->gen, seen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      ok = wait_epoch(ctl, seen, timeout);
+    }
+    seen++;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  return ok;
+}
+
+// pointer jumping over one net's cells by one workgroup (`flag`: an LDS word)
+template <int WG>
+__device__ __forceinline__ void jump_net(gint *__restrict__ bind, int n_cells, int *flag) {
+  for (int round = 0; round < 32; round++) {
+    if (threadIdx.x == 0) *flag = 0;
+    __syncthreads();
+    bool moved = false;
+    for (int x = threadIdx.x; x < n_cells; x += WG) moved |= jump_hop(bind, x);
+    if (moved) *flag = 1;
+    __syncthreads();
+    const int again = *flag;
+    __syncthreads();
+    if (!again) break;
+  }
+}
+
+// LDS state of one net engine (one workgroup)
+template <int QCAP>
+struct EngineLds {
+  Pair q[2][QCAP + 64];  // frontier double buffer (+ a spare slot per lane, for the append)
+  int cnt[3];
+  int net;
+  int agent_top, name_top, status, nstuck, loops, maxf;
+  unsigned steps;  // hand-over from one-wave steps (engine 3)
+  int cur;
+  unsigned long long rc[MAXRULES];
+  int bcast[8];    // values broadcast to the workgroup (multi-workgroup engine)
+};
+
+// The rule table in LDS: rule_of[ns*ns] | templates[nr][RT_WORDS] | arity[ns]
+struct RuleView {
+  const int *rule_of, *templ, *arity;            // LDS
+  const int *__restrict__ g_templ, *__restrict__ g_arity;  // global (scalar reads)
+  int ns, nr;
+};
+
+// One net on one workgroup, from its saved state: the initial equations are
+// linked (first launch), then parallel steps run until no active pair is
+// left, the absolute step budget `stop` is reached, an error occurs, or more
+// than `hi` pairs are active (a multi-workgroup engine then takes the net
+// over); the state is saved back into the net's NetState and queues.  With
+// `hb`, the step count is published there every 1024 steps (progress seen by
+// workgroups waiting on this one).
+template <int WG, int QCAP, int ENGINE, int MAXL>
+__device__ __forceinline__ void engine_net(EngineLds<QCAP> &S, const NetDesc &D, const RuleView &RV,
+                                           unsigned stop, int flags, int hi, const KParams &kp,
+                                           int *hb) {
+  const int tid = threadIdx.x;
+  const int *rule_of = RV.rule_of;
+  const int nr = RV.nr;
+  NetState *st = D.st;
+  gint *const agent = (gint *)D.agent;
+  gint *const bind = (gint *)D.bind;
+  gint2 *const queue0 = (gint2 *)D.queue0;
+  gint2 *const queue1 = (gint2 *)D.queue1;
+  gint2 *const stuck = (gint2 *)D.stuck;
+  const int phase = st->phase;
+  if (phase == PHASE_DONE || st->status == ST_ENOMEM || st->status == ST_EINTERNAL ||
+      st->status == ST_ETIMEDOUT)
+    return;
+  const int nfront = st->frontier;
+  int cur = st->parity;
+  unsigned steps = st->steps;
+  if (tid == 0) {
+    S.agent_top = st->agent_top;
+    S.name_top = st->name_top;
+    S.status = 0;
+    S.nstuck = st->n_stuck;
+    S.loops = 0;
+    S.maxf = st->max_frontier;
+    S.cnt[0] = (phase == PHASE_INIT) ? 0 : nfront;
+    S.cnt[1] = 0;
+    S.cnt[2] = 0;
+  }
+  for (int r = tid; r < nr; r += WG) S.rc[r] = 0ull;
+  int ci = 0;
+  if (phase == PHASE_INIT) {
+    // the initial equations (queue0) are linked into buffer 1 (counter 1)
+    __syncthreads();
+    for (int base = 0; base < nfront; base += WG) {
+      const int i = base + tid;
+      const bool valid = i < nfront;
+      Pair e = mkpair(0, 0);
+      if (valid) e = unpk(queue0[i]);
+      int ou = 0, ov = 0, loops = 0;
+      const bool prod = valid && link(e.x, e.y, bind, (unsigned)D.name_cap, ou, ov, loops, &S.status);
+      wave_push(prod, ou, ov, S.q[1], QCAP, queue1, D.qcap, &S.cnt[1], &S.status);
+      if (loops) atomicAdd(&S.loops, loops);
+    }
+    cur = 1;
+    ci = 1;
+  } else {
+    gint2 *g = cur ? queue1 : queue0;
+    const int nl = nfront < QCAP ? nfront : QCAP;
+    for (int i = tid; i < nl; i += WG) S.q[cur][i] = unpk(g[i]);
+  }
+
+#ifdef INET_STATIC_RULES
+  if constexpr (ENGINE == 3 || ENGINE == 4) {
+    // engine 4 reserves heap and frontier space per lane (atomic append);
+    // its counters are shared words, so it always steps as a group
+    constexpr bool LANE = ENGINE == 4;
+    unsigned rc_lane = 0;  // lane r of each wave: interactions of rule r in this launch
+    int loops_lane = 0;    // closed loops dropped by this lane
+    // Steps of wave 0 alone, while the frontier holds at most `limit` pairs:
+    // the counters live in registers and no barrier separates steps (a
+    // wave's own memory operations are performed in order).  The other waves
+    // of a wider engine wait at the caller's barrier meanwhile.  On return
+    // the state is back in LDS, with the frontier count in S.cnt[ci].
+    // While the pairs of a step fit the wave, each lane keeps its first new
+    // pair in registers for the next step (no LDS round trip); only the
+    // others go through the LDS frontier, and lanes without a pair take
+    // them by rank.  Wider steps run from the LDS frontier in chunks.
+    auto solo = [&](int limit) {
+      Ctr<CM_REG> C;
+      C.agent_top = __builtin_amdgcn_readfirstlane(S.agent_top);
+      C.name_top = __builtin_amdgcn_readfirstlane(S.name_top);
+      C.nstuck = __builtin_amdgcn_readfirstlane(S.nstuck);
+      C.err = __builtin_amdgcn_readfirstlane(S.status);
+      C.next = 0;
+      int n = __builtin_amdgcn_readfirstlane(S.cnt[ci]);  // pairs in the frontier q[cur]
+      int maxf = __builtin_amdgcn_readfirstlane(S.maxf);
+      int ha = -1, hb_ = 0;  // the lane's held pair (ha < 0: none)
+      int nh = 0;            // held pairs of the wave
+      // the held pairs back into the frontier, after its n pairs
+      auto release = [&]() {
+        if (nh) {
+          const unsigned long long hm = ballot(ha >= 0);
+          bool over = false;
+          if (ha >= 0) {
+            const int i = n + count_below(hm);
+            if (i < QCAP) S.q[cur][i] = mkpair(ha, hb_);
+            else if (i < D.qcap) *at2(cur ? queue1 : queue0, (unsigned)i) = pk(ha, hb_);
+            else over = true;
+          }
+          C.fail(over, false);
+          n += nh;
+          nh = 0;
+          ha = -1;
+        }
+      };
+      for (;;) {
+        const int tot = n + nh;
+        if (!(tot > 0 && tot <= limit && C.err >= 0 && steps < stop)) break;
+        if (tot > maxf) maxf = tot;
+        if (hb && (steps & 1023u) == 0 && __lane_id() == 0) gstore(hb, (int)steps);
+        const Pair *cq_l = S.q[cur];
+        const gint2 *cq_g = cur ? queue1 : queue0;
+        Pair *nq_l = S.q[cur ^ 1];
+        gint2 *nq_g = cur ? queue0 : queue1;
+        C.next = 0;
+        int nha = -1, nhb = 0;
+        if (tot <= 64) {
+          // held pairs stay with their lanes; the n frontier pairs (all in
+          // the LDS tile: n <= 64) go to the free lanes by rank
+          const int r = count_below(ballot(ha < 0));
+          const bool take = ha < 0 && r < n;
+          const Pair rx = cq_l[take ? r : 0];
+          const bool valid = ha >= 0 || take;
+          const int a = ha >= 0 ? ha : (take ? rx.x : 0);
+          const int b = ha >= 0 ? hb_ : (take ? rx.y : 0);
+          const v4i ra = *rec(agent, (unsigned)a), rb = *rec(agent, (unsigned)b);
+          pass_static<QCAP, MAXL, CM_REG, false, true>(valid, a, b, ra.x, rb.x, ra.y, ra.z, rb.y,
+                                                       rb.z, D, agent, bind, stuck, rule_of, nq_l,
+                                                       nq_g, C, loops_lane, rc_lane, nha, nhb);
+        } else {
+          release();
+          for (int base = 0; base < n; base += 64) {
+            bool valid;
+            int a, b, la, lb, pa0, pa1, pb0, pb1;
+            fetch_pair<64, QCAP>(base, n, tid, cq_l, cq_g, agent, valid, a, b, la, lb, pa0,
+                                 pa1, pb0, pb1);
+            pass_static<QCAP, MAXL, CM_REG, false>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D,
+                                                   agent, bind, stuck, rule_of, nq_l, nq_g, C,
+                                                   loops_lane, rc_lane, nha, nhb);
+          }
+        }
+        // lanes of one wave need no cache action or wait to see each
+        // other's writes (wavefront scope); the fence only keeps the
+        // compiler from moving memory operations across steps
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        steps++;
+        cur ^= 1;
+        n = C.next;
+        ha = nha;
+        hb_ = nhb;
+        nh = __popcll(ballot(ha >= 0));
+      }
+      release();  // the frontier whole in q[cur] again, for the caller
+      if (tid == 0) {
+        S.cnt[ci] = n;
+        S.cnt[ci == 2 ? 0 : ci + 1] = 0;
+        S.cnt[ci == 0 ? 2 : ci - 1] = 0;
+        S.agent_top = C.agent_top;
+        S.name_top = C.name_top;
+        S.nstuck = C.nstuck;
+        S.maxf = maxf;
+        S.steps = steps;
+        S.cur = cur;
+        if (C.err < 0) S.status = C.err;
+      }
+    };
+    const int solo_max = kp.solo_max < hi ? kp.solo_max : hi;
+    if constexpr (WG == 64 && !LANE) {
+      __syncthreads();
+      solo(hi);
+      if (rc_lane) atomicAdd(&S.rc[tid], (unsigned long long)rc_lane);
+      if (loops_lane) atomicAdd(&S.loops, loops_lane);
+      __syncthreads();
+    } else {
+      // a wider engine: all waves step together while the frontier is wider
+      // than solo_max pairs, wave 0 alone while it is not
+      Ctr<CM_LDS> C;
+      C.agent_top = &S.agent_top;
+      C.name_top = &S.name_top;
+      C.nstuck = &S.nstuck;
+      C.status = &S.status;
+      for (;;) {
+        __syncthreads();
+        const int n = S.cnt[ci];
+        if (n == 0 || S.status < 0 || steps >= stop || n > hi) break;
+        if (!LANE && n <= solo_max) {
+          if (tid < 64) solo(solo_max);
+          __syncthreads();
+          steps = S.steps;
+          cur = S.cur;
+          continue;
+        }
+        const int cn = ci == 2 ? 0 : ci + 1;
+        const int cnn = cn == 2 ? 0 : cn + 1;
+        if (tid == 0) {
+          S.cnt[cnn] = 0;
+          if (n > S.maxf) S.maxf = n;
+          if (hb && (steps & 1023u) == 0) gstore(hb, (int)steps);
+        }
+        const Pair *cq_l = S.q[cur];
+        const gint2 *cq_g = cur ? queue1 : queue0;
+        Pair *nq_l = S.q[cur ^ 1];
+        gint2 *nq_g = cur ? queue0 : queue1;
+        C.next = &S.cnt[cn];
+        for (int base = 0; base < n; base += WG) {
+          bool valid;
+          int a, b, la, lb, pa0, pa1, pb0, pb1;
+          fetch_pair<WG, QCAP>(base, n, tid, cq_l, cq_g, agent, valid, a, b, la, lb, pa0, pa1,
+                               pb0, pb1);
+          int nha, nhb;
+          pass_static<QCAP, MAXL, CM_LDS, LANE>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, agent,
+                                                bind, stuck, rule_of, nq_l, nq_g, C,
+                                                loops_lane, rc_lane, nha, nhb);
+        }
+        steps++;
+        cur ^= 1;
+        ci = cn;
+      }
+      if (rc_lane) atomicAdd(&S.rc[__lane_id()], (unsigned long long)rc_lane);
+      if (loops_lane) atomicAdd(&S.loops, loops_lane);
+      __syncthreads();
+    }
+  } else
+#endif
+  for (;;) {
+    __syncthreads();
+    const int n = S.cnt[ci];
+    if (n == 0 || S.status < 0 || steps >= stop || n > hi) break;
+    const int cn = ci == 2 ? 0 : ci + 1;
+    const int cnn = cn == 2 ? 0 : cn + 1;
+    if (tid == 0) {
+      S.cnt[cnn] = 0;
+      if (n > S.maxf) S.maxf = n;
+    }
+    const Pair *cq_l = S.q[cur];
+    const gint2 *cq_g = cur ? queue1 : queue0;
+    Pair *nq_l = S.q[cur ^ 1];
+    gint2 *nq_g = cur ? queue0 : queue1;
+    for (int base = 0; base < n; base += WG) {
+      const int i = base + tid;
+      const bool valid = i < n;
+      // lanes without a pair read slot 0 (always allocated) and stay idle:
+      // the loads need no branch
+      Pair rx = mkpair(0, 0);
+      if (base + WG <= QCAP) {
+        rx = cq_l[valid ? i : 0];
+      } else if (valid) {
+        if (i < QCAP) rx = cq_l[i];
+        else rx = unpk(*at2((gint2 *)cq_g, (unsigned)i));
+      }
+      if (!valid) rx = mkpair(0, 0);
+      const int a = rx.x, b = rx.y;
+      const unsigned ua = (unsigned)a, ub = (unsigned)b;
+      const v4i ra = *rec(agent, ua), rb = *rec(agent, ub);
+      const int la = ra.x, lb = rb.x;
+      const int pa0 = ra.y, pa1 = ra.z;
+      const int pb0 = rb.y, pb1 = rb.z;
+      if constexpr (ENGINE == 1)
+        pass_interp<QCAP>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, agent, bind,
+                          stuck, rule_of, RV.templ, RV.arity, RV.g_templ, RV.g_arity, RV.ns, nq_l, nq_g,
+                          &S.cnt[cn], &S.status, &S.agent_top, &S.name_top, &S.nstuck, &S.loops,
+                          S.rc);
+      else
+        pass_uniform<QCAP, MAXL>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, agent, bind,
+                                 stuck, rule_of, RV.templ, RV.arity, RV.g_templ, RV.g_arity, RV.ns,
+                                 nq_l, nq_g, &S.cnt[cn], &S.status, &S.agent_top, &S.name_top,
+                                 &S.nstuck, &S.loops, S.rc);
+    }
+    steps++;
+    cur ^= 1;
+    ci = cn;
+  }
+
+  // the loop ends right after a barrier with uniform values
+  const int n_left = S.cnt[ci];
+  const int status = S.status;
+  if (status >= 0 && n_left > 0) {
+    gint2 *g = cur ? queue1 : queue0;
+    const int nl = n_left < QCAP ? n_left : QCAP;
+    for (int i = tid; i < nl; i += WG) g[i] = pk(S.q[cur][i].x, S.q[cur][i].y);
+  }
+  gu64 *per_rule = (gu64 *)D.per_rule;
+  for (int r = tid; r < nr; r += WG)
+    if (S.rc[r]) per_rule[r] += S.rc[r];
+  const bool done = status >= 0 && n_left == 0;
+  if (tid == 0) {
+    unsigned long long tot = 0;
+    for (int r = 0; r < nr; r++) tot += S.rc[r];
+    st->interactions += tot;
+    st->steps = steps;
+    st->agent_top = S.agent_top;
+    st->name_top = S.name_top;
+    st->n_stuck = S.nstuck;
+    st->loops += S.loops;
+    st->max_frontier = S.maxf;
+    if (status < 0) {
+      st->status = status;
+    } else if (!done) {
+      // stopped by the step budget (resumable), or handed over while wide
+      st->phase = PHASE_RUN;
+      st->parity = cur;
+      st->frontier = n_left;
+      st->status = steps >= stop ? ST_ELIMIT : ST_OK;
+    } else {
+      st->phase = PHASE_DONE;
+      st->frontier = 0;
+      st->status = S.nstuck ? ST_STUCK : ST_OK;
+    }
+  }
+  if ((flags & FLAG_JUMP) && done) {
+    __syncthreads();
+    jump_net<WG>(bind, S.name_top, &S.bcast[0]);
+  }
+}
+
+template <int WG, int QCAP>
+__device__ __forceinline__ RuleView load_rules(const int *__restrict__ g_rules, int ns, int nr,
+                                               int *s_rules) {
+  const int nwords = ns * ns + nr * RT_WORDS + ns;
+  for (int i = threadIdx.x; i < nwords; i += WG) s_rules[i] = g_rules[i];
+  RuleView RV;
+  RV.rule_of = s_rules;
+  RV.templ = s_rules + ns * ns;
+  RV.arity = RV.templ + nr * RT_WORDS;
+  RV.g_templ = g_rules + ns * ns;
+  RV.g_arity = RV.g_templ + nr * RT_WORDS;
+  RV.ns = ns;
+  RV.nr = nr;
+  return RV;
+}
+
+// the persistent batch kernel: each workgroup takes nets from a device
+// counter in the given order and runs each to normal form (or the budget)
 template <int WG, int QCAP, int ENGINE, int MAXL>
 __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
                                             const int *__restrict__ order, int n_nets,
                                             int *counter, const int *__restrict__ g_rules,
-                                            int ns, int nr, unsigned max_steps, int flags) {
+                                            int ns, int nr, unsigned max_steps, int flags,
+                                            const KParams &kp) {
   extern __shared__ int s_rules[];
-  __shared__ Pair q[2][QCAP + 64];  // + a spare slot per lane (append)
-  __shared__ int s_cnt[3];
-  __shared__ int s_net;
-  __shared__ int s_agent_top, s_name_top, s_status, s_nstuck, s_loops, s_maxf;
-  __shared__ unsigned s_steps;  // hand-over from one-wave steps (engine 3)
-  __shared__ int s_cur;
-  __shared__ unsigned long long s_rc[MAXRULES];
-
-  const int tid = threadIdx.x;
-  const int nwords = ns * ns + nr * RT_WORDS + ns;
-  for (int i = tid; i < nwords; i += WG) s_rules[i] = g_rules[i];
-  const int *rule_of = s_rules;
-  const int *templ = s_rules + ns * ns;
-  const int *arity = templ + nr * RT_WORDS;
-  const int *__restrict__ g_templ = g_rules + ns * ns;
-  const int *__restrict__ g_arity = g_templ + nr * RT_WORDS;
-
+  __shared__ EngineLds<QCAP> S;
+  const RuleView RV = load_rules<WG, QCAP>(g_rules, ns, nr, s_rules);
   for (;;) {
     __syncthreads();
-    if (tid == 0) s_net = atomicAdd(counter, 1);
+    if (threadIdx.x == 0) S.net = atomicAdd(counter, 1);
     __syncthreads();
-    const int k = __builtin_amdgcn_readfirstlane(s_net);
+    const int k = __builtin_amdgcn_readfirstlane(S.net);
     if (k >= n_nets) break;
     const NetDesc D = descs[order[k]];
-    NetState *st = D.st;
-    gint *const agent = (gint *)D.agent;
-    gint *const bind = (gint *)D.bind;
-    gint2 *const queue0 = (gint2 *)D.queue0;
-    gint2 *const queue1 = (gint2 *)D.queue1;
-    gint2 *const stuck = (gint2 *)D.stuck;
-    const int phase = st->phase;
-    if (phase == PHASE_DONE || st->status == ST_ENOMEM || st->status == ST_EINTERNAL) continue;
-    const int nfront = st->frontier;
-    int cur = st->parity;
-    unsigned steps = st->steps;
+    const unsigned steps0 = D.st->steps;
     // per-launch step budget (saturating)
-    const unsigned stop = (max_steps > 0xffffffffu - steps) ? 0xffffffffu : steps + max_steps;
-    if (tid == 0) {
-      s_agent_top = st->agent_top;
-      s_name_top = st->name_top;
-      s_status = 0;
-      s_nstuck = st->n_stuck;
-      s_loops = 0;
-      s_maxf = st->max_frontier;
-      s_cnt[0] = (phase == PHASE_INIT) ? 0 : nfront;
-      s_cnt[1] = 0;
-      s_cnt[2] = 0;
-    }
-    for (int r = tid; r < nr; r += WG) s_rc[r] = 0ull;
-    int ci = 0;
-    if (phase == PHASE_INIT) {
-      // the initial equations (queue0) are linked into buffer 1 (counter 1)
-      __syncthreads();
-      for (int base = 0; base < nfront; base += WG) {
-        const int i = base + tid;
-        const bool valid = i < nfront;
-        Pair e = mkpair(0, 0);
-        if (valid) e = unpk(queue0[i]);
-        int ou = 0, ov = 0, loops = 0;
-        const bool prod = valid && link(e.x, e.y, bind, (unsigned)D.name_cap, ou, ov, loops, &s_status);
-        wave_push(prod, ou, ov, q[1], QCAP, queue1, D.qcap, &s_cnt[1], &s_status);
-        if (loops) atomicAdd(&s_loops, loops);
-      }
-      cur = 1;
-      ci = 1;
-    } else {
-      gint2 *g = cur ? queue1 : queue0;
-      const int nl = nfront < QCAP ? nfront : QCAP;
-      for (int i = tid; i < nl; i += WG) q[cur][i] = unpk(g[i]);
-    }
-
-#ifdef INET_STATIC_RULES
-    if constexpr (ENGINE == 3 || ENGINE == 4) {
-      // engine 4 reserves heap and frontier space per lane (atomic append);
-      // its counters are shared words, so it always steps as a group
-      constexpr bool LANE = ENGINE == 4;
-      unsigned rc_lane = 0;  // lane r of each wave: interactions of rule r in this launch
-      int loops_lane = 0;    // closed loops dropped by this lane
-      // Steps of wave 0 alone, while the frontier holds at most `limit` pairs:
-      // the counters live in registers and no barrier separates steps (a
-      // wave's own memory operations are performed in order).  The other waves
-      // of a wider engine wait at the caller's barrier meanwhile.  On return
-      // the state is back in LDS, with the frontier count in s_cnt[ci].
-      // While the pairs of a step fit the wave, each lane keeps its first new
-      // pair in registers for the next step (no LDS round trip); only the
-      // others go through the LDS frontier, and lanes without a pair take
-      // them by rank.  Wider steps run from the LDS frontier in chunks.
-      auto solo = [&](int limit) {
-        Ctr<true> C;
-        C.agent_top = __builtin_amdgcn_readfirstlane(s_agent_top);
-        C.name_top = __builtin_amdgcn_readfirstlane(s_name_top);
-        C.nstuck = __builtin_amdgcn_readfirstlane(s_nstuck);
-        C.err = __builtin_amdgcn_readfirstlane(s_status);
-        C.next = 0;
-        int n = __builtin_amdgcn_readfirstlane(s_cnt[ci]);  // pairs in the frontier q[cur]
-        int maxf = __builtin_amdgcn_readfirstlane(s_maxf);
-        int ha = -1, hb = 0;  // the lane's held pair (ha < 0: none)
-        int nh = 0;           // held pairs of the wave
-        // the held pairs back into the frontier, after its n pairs
-        auto release = [&]() {
-          if (nh) {
-            const unsigned long long hm = ballot(ha >= 0);
-            bool over = false;
-            if (ha >= 0) {
-              const int i = n + count_below(hm);
-              if (i < QCAP) q[cur][i] = mkpair(ha, hb);
-              else if (i < D.qcap) *at2(cur ? queue1 : queue0, (unsigned)i) = pk(ha, hb);
-              else over = true;
-            }
-            C.fail(over, false);
-            n += nh;
-            nh = 0;
-            ha = -1;
-          }
-        };
-        for (;;) {
-          const int tot = n + nh;
-          if (!(tot > 0 && tot <= limit && C.err >= 0 && steps < stop)) break;
-          if (tot > maxf) maxf = tot;
-          const Pair *cq_l = q[cur];
-          const gint2 *cq_g = cur ? queue1 : queue0;
-          Pair *nq_l = q[cur ^ 1];
-          gint2 *nq_g = cur ? queue0 : queue1;
-          C.next = 0;
-          int nha = -1, nhb = 0;
-          if (tot <= 64) {
-            // held pairs stay with their lanes; the n frontier pairs (all in
-            // the LDS tile: n <= 64) go to the free lanes by rank
-            const int r = count_below(ballot(ha < 0));
-            const bool take = ha < 0 && r < n;
-            const Pair rx = cq_l[take ? r : 0];
-            const bool valid = ha >= 0 || take;
-            const int a = ha >= 0 ? ha : (take ? rx.x : 0);
-            const int b = ha >= 0 ? hb : (take ? rx.y : 0);
-            const v4i ra = *rec(agent, (unsigned)a), rb = *rec(agent, (unsigned)b);
-            pass_static<QCAP, MAXL, true, false, true>(valid, a, b, ra.x, rb.x, ra.y, ra.z, rb.y,
-                                                       rb.z, D, agent, bind, stuck, rule_of, nq_l,
-                                                       nq_g, C, loops_lane, rc_lane, nha, nhb);
-          } else {
-            release();
-            for (int base = 0; base < n; base += 64) {
-              bool valid;
-              int a, b, la, lb, pa0, pa1, pb0, pb1;
-              fetch_pair<64, QCAP>(base, n, tid, cq_l, cq_g, agent, valid, a, b, la, lb, pa0,
-                                   pa1, pb0, pb1);
-              pass_static<QCAP, MAXL, true, false>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D,
-                                                   agent, bind, stuck, rule_of, nq_l, nq_g, C,
-                                                   loops_lane, rc_lane, nha, nhb);
-            }
-          }
-          // lanes of one wave need no cache action or wait to see each
-          // other's writes (wavefront scope); the fence only keeps the
-          // compiler from moving memory operations across steps
-          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-          steps++;
-          cur ^= 1;
-          n = C.next;
-          ha = nha;
-          hb = nhb;
-          nh = __popcll(ballot(ha >= 0));
-        }
-        release();  // the frontier whole in q[cur] again, for the caller
-        if (tid == 0) {
-          s_cnt[ci] = n;
-          s_cnt[ci == 2 ? 0 : ci + 1] = 0;
-          s_cnt[ci == 0 ? 2 : ci - 1] = 0;
-          s_agent_top = C.agent_top;
-          s_name_top = C.name_top;
-          s_nstuck = C.nstuck;
-          s_maxf = maxf;
-          s_steps = steps;
-          s_cur = cur;
-          if (C.err < 0) s_status = C.err;
-        }
-      };
-      if constexpr (WG == 64 && !LANE) {
-        __syncthreads();
-        solo(0x7fffffff);
-        if (rc_lane) atomicAdd(&s_rc[tid], (unsigned long long)rc_lane);
-        if (loops_lane) atomicAdd(&s_loops, loops_lane);
-        __syncthreads();
-      } else {
-        // a wider engine: all waves step together while the frontier is wider
-        // than one wave, wave 0 alone while it is not
-        Ctr<false> C;
-        C.agent_top = &s_agent_top;
-        C.name_top = &s_name_top;
-        C.nstuck = &s_nstuck;
-        C.status = &s_status;
-        for (;;) {
-          __syncthreads();
-          const int n = s_cnt[ci];
-          if (n == 0 || s_status < 0 || steps >= stop) break;
-          if (!LANE && n <= 64) {
-            if (tid < 64) solo(64);
-            __syncthreads();
-            steps = s_steps;
-            cur = s_cur;
-            continue;
-          }
-          const int cn = ci == 2 ? 0 : ci + 1;
-          const int cnn = cn == 2 ? 0 : cn + 1;
-          if (tid == 0) {
-            s_cnt[cnn] = 0;
-            if (n > s_maxf) s_maxf = n;
-          }
-          const Pair *cq_l = q[cur];
-          const gint2 *cq_g = cur ? queue1 : queue0;
-          Pair *nq_l = q[cur ^ 1];
-          gint2 *nq_g = cur ? queue0 : queue1;
-          C.next = &s_cnt[cn];
-          for (int base = 0; base < n; base += WG) {
-            bool valid;
-            int a, b, la, lb, pa0, pa1, pb0, pb1;
-            fetch_pair<WG, QCAP>(base, n, tid, cq_l, cq_g, agent, valid, a, b, la, lb, pa0, pa1,
-                                 pb0, pb1);
-            int nha, nhb;
-            pass_static<QCAP, MAXL, false, LANE>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, agent,
-                                           bind, stuck, rule_of, nq_l, nq_g, C,
-                                           loops_lane, rc_lane, nha, nhb);
-          }
-          steps++;
-          cur ^= 1;
-          ci = cn;
-        }
-        if (rc_lane) atomicAdd(&s_rc[__lane_id()], (unsigned long long)rc_lane);
-        if (loops_lane) atomicAdd(&s_loops, loops_lane);
-        __syncthreads();
-      }
-    } else
-#endif
-    for (;;) {
-      __syncthreads();
-      const int n = s_cnt[ci];
-      if (n == 0 || s_status < 0 || steps >= stop) break;
-      const int cn = ci == 2 ? 0 : ci + 1;
-      const int cnn = cn == 2 ? 0 : cn + 1;
-      if (tid == 0) {
-        s_cnt[cnn] = 0;
-        if (n > s_maxf) s_maxf = n;
-      }
-      const Pair *cq_l = q[cur];
-      const gint2 *cq_g = cur ? queue1 : queue0;
-      Pair *nq_l = q[cur ^ 1];
-      gint2 *nq_g = cur ? queue0 : queue1;
-      for (int base = 0; base < n; base += WG) {
-        const int i = base + tid;
-        const bool valid = i < n;
-        // lanes without a pair read slot 0 (always allocated) and stay idle:
-        // the loads need no branch
-        Pair rx = mkpair(0, 0);
-        if (base + WG <= QCAP) {
-          rx = cq_l[valid ? i : 0];
-        } else if (valid) {
-          if (i < QCAP) rx = cq_l[i];
-          else rx = unpk(*at2((gint2 *)cq_g, (unsigned)i));
-        }
-        if (!valid) rx = mkpair(0, 0);
-        const int a = rx.x, b = rx.y;
-        const unsigned ua = (unsigned)a, ub = (unsigned)b;
-        const v4i ra = *rec(agent, ua), rb = *rec(agent, ub);
-        const int la = ra.x, lb = rb.x;
-        const int pa0 = ra.y, pa1 = ra.z;
-        const int pb0 = rb.y, pb1 = rb.z;
-        if constexpr (ENGINE == 1)
-          pass_interp<QCAP>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, agent, bind,
-                            stuck, rule_of, templ, arity, g_templ, g_arity, ns, nq_l, nq_g,
-                            &s_cnt[cn], &s_status, &s_agent_top, &s_name_top, &s_nstuck, &s_loops,
-                            s_rc);
-        else
-          pass_uniform<QCAP, MAXL>(valid, a, b, la, lb, pa0, pa1, pb0, pb1, D, agent, bind,
-                             stuck, rule_of, templ, arity, g_templ, g_arity, ns, nq_l, nq_g,
-                             &s_cnt[cn], &s_status, &s_agent_top, &s_name_top, &s_nstuck, &s_loops,
-                             s_rc);
-      }
-      steps++;
-      cur ^= 1;
-      ci = cn;
-    }
-
-    // the loop ends right after a barrier with uniform values
-    const int n_left = s_cnt[ci];
-    const int status = s_status;
-    if (status >= 0 && n_left > 0) {
-      gint2 *g = cur ? queue1 : queue0;
-      const int nl = n_left < QCAP ? n_left : QCAP;
-      for (int i = tid; i < nl; i += WG) g[i] = pk(q[cur][i].x, q[cur][i].y);
-    }
-    gu64 *per_rule = (gu64 *)D.per_rule;
-    for (int r = tid; r < nr; r += WG)
-      if (s_rc[r]) per_rule[r] += s_rc[r];
-    const bool done = status >= 0 && n_left == 0;
-    if (tid == 0) {
-      unsigned long long tot = 0;
-      for (int r = 0; r < nr; r++) tot += s_rc[r];
-      st->interactions += tot;
-      st->steps = steps;
-      st->agent_top = s_agent_top;
-      st->name_top = s_name_top;
-      st->n_stuck = s_nstuck;
-      st->loops += s_loops;
-      st->max_frontier = s_maxf;
-      if (status < 0) {
-        st->status = status;
-      } else if (!done) {
-        st->phase = PHASE_RUN;
-        st->parity = cur;
-        st->frontier = n_left;
-        st->status = ST_ELIMIT;
-      } else {
-        st->phase = PHASE_DONE;
-        st->frontier = 0;
-        st->status = s_nstuck ? ST_STUCK : ST_OK;
-      }
-    }
-    if ((flags & FLAG_JUMP) && done) {
-      __syncthreads();
-      jump_cells(bind, tid, s_name_top, WG);
-    }
+    const unsigned stop = (max_steps > 0xffffffffu - steps0) ? 0xffffffffu : steps0 + max_steps;
+    engine_net<WG, QCAP, ENGINE, MAXL>(S, D, RV, stop, flags, 0x7fffffff, kp, nullptr);
   }
 }
+
+#ifdef INET_STATIC_RULES
+// ---------------------------------------------------------------------------
+// Multi-workgroup engine for one net (the launch's only net).  Workgroup 0
+// steps the net alone (engine_net, one compute unit) while at most grid_hi
+// pairs are active; once more are, the net's parallel steps are shared by the
+// g workgroups of lowest logical index, g = ceil(active / grid_ppw) up to the
+// whole launch, until at most grid_lo pairs are left.  In such a step each
+// participating workgroup takes a contiguous share of the frontier (global
+// queue), runs the same pass as the one-workgroup engine with the heap tops
+// and status as agent-scope atomics in the net's state, stages its new active
+// pairs in its LDS tile and appends them to the next frontier with one
+// agent-scope atomic.  Steps are separated by a barrier over the launch:
+// agent-scope release before arriving, acquire after leaving, so that agent
+// records, name cells and queue entries written in a step are seen by every
+// workgroup in the next (the name-cell exchanges themselves are agent-scope
+// atomics).  Every wait at the barrier gives up after kp.timeout wall-clock
+// ticks without progress (a new epoch, or workgroup 0's step count moving),
+// setting ST_ETIMEDOUT, so the kernel always ends.
+
+// logical index of block b of G: blocks are handed to the XCDs in turn
+// (block b runs on XCD b % 8), so logical indices run through one XCD's
+// blocks before the next one's; a small group of participants then shares
+// one L2
+__device__ __forceinline__ int logical_wg(int b, int G) {
+  const int x = b & 7;
+  int before = 0;
+  for (int k = 0; k < x; k++) before += (G - k + 7) >> 3;  // blocks on XCD k
+  return before + (b >> 3);
+}
+
+template <int WG, int QCAP, int MAXL>
+__device__ __forceinline__ void grid_body(const NetDesc *__restrict__ descs,
+                                          const int *__restrict__ g_rules, int ns, int nr,
+                                          unsigned max_steps, int flags, const KParams &kp) {
+  extern __shared__ int s_rules[];
+  __shared__ EngineLds<QCAP> S;
+  const RuleView RV = load_rules<WG, QCAP>(g_rules, ns, nr, s_rules);
+  const NetDesc D = descs[0];
+  NetState *st = D.st;
+  GridCtl *ctl = kp.ctl;
+  const int tid = threadIdx.x;
+  const int G = gridDim.x;
+  const int me = logical_wg(blockIdx.x, G);
+  gint *const agent = (gint *)D.agent;
+  gint *const bind = (gint *)D.bind;
+  gint2 *const stuck = (gint2 *)D.stuck;
+  const int lo = kp.grid_lo, hi = kp.grid_hi > kp.grid_lo ? kp.grid_hi : kp.grid_lo;
+  unsigned rc_lane = 0;
+  int loops_lane = 0;
+  int seen = 0;
+  // epoch 0: workgroup 0 steps the net alone (linking the initial equations
+  // on the first launch) until it widens or ends
+  bool part = me == 0;
+  int mode = GM_NARROW;
+  unsigned stop = 0;  // absolute step budget (workgroup 0 only)
+  if (me == 0) {
+    const unsigned steps0 = st->steps;
+    stop = (max_steps > 0xffffffffu - steps0) ? 0xffffffffu : steps0 + max_steps;
+    if (tid == 0) ctl->stop = stop;
+    engine_net<WG, QCAP, 3, MAXL>(S, D, RV, stop, 0, hi, kp, &ctl->heartbeat);
+  }
+  for (;;) {
+    // ---- barrier between epochs
+    __syncthreads();
+    if (tid == 0) {
+      bool ok = true;
+      if (part) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const int target = seen == 0 ? 1 : gload(&ctl->target);
+        if (gadd(&ctl->arrive, 1) == target - 1) {
+          // the last to arrive decides the next epoch
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          int n, cur, status;
+          unsigned steps;
+          const unsigned stp = ctl->stop;
+          if (mode == GM_GRID) {
+            n = gload(&ctl->next);
+            cur = ctl->cur ^ 1;
+            steps = ctl->steps + 1;
+            const int done_n = ctl->n;
+            if (done_n > st->max_frontier) st->max_frontier = done_n;
+          } else {
+            n = st->frontier;
+            cur = st->parity;
+            steps = st->steps;
+            if (st->phase == PHASE_DONE) n = 0;
+          }
+          // a give-up recorded by any workgroup ends the launch with it
+          // (workgroup 0's own bookkeeping may have written over the status)
+          if (gload(&ctl->gave_up)) gstore(&st->status, ST_ETIMEDOUT);
+          status = gload(&st->status);
+          int next_mode, g = 1;
+          if (n == 0 || status < 0 || steps >= stp) {
+            next_mode = GM_DONE;
+            if (mode == GM_GRID) {
+              // the net's state as the one-workgroup engine leaves it
+              st->steps = steps;
+              if (status >= 0) {
+                if (n == 0) {
+                  st->phase = PHASE_DONE;
+                  st->frontier = 0;
+                  gstore(&st->status, gload(&st->n_stuck) ? ST_STUCK : ST_OK);
+                } else {
+                  st->phase = PHASE_RUN;
+                  st->parity = cur;
+                  st->frontier = n;
+                  gstore(&st->status, ST_ELIMIT);
+                }
+              }
+            }
+          } else if (n <= lo) {
+            next_mode = GM_NARROW;
+            st->phase = PHASE_RUN;
+            st->parity = cur;
+            st->frontier = n;
+            st->steps = steps;
+          } else {
+            next_mode = GM_GRID;
+            const int ppw = kp.grid_ppw > 0 ? kp.grid_ppw : WG;
+            g = (n + ppw - 1) / ppw;
+            if (g > G) g = G;
+            if (g < 1) g = 1;
+          }
+          ctl->mode = next_mode;
+          ctl->n = n;
+          ctl->cur = cur;
+          ctl->g = g;
+          ctl->target = next_mode == GM_GRID ? g : 1;
+          ctl->steps = steps;
+          gstore(&ctl->next, 0);
+          gstore(&ctl->arrive, 0);
+          __hip_atomic_store(&ctl->gen, seen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+          ok = wait_epoch(ctl, seen, kp.timeout);
+        }
+      } else {
+        ok = wait_epoch(ctl, seen, kp.timeout);
+      }
+      if (!ok) {
+        gstore(&ctl->gave_up, 1);
+        gstore(&st->status, ST_ETIMEDOUT);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      S.bcast[0] = ok ? ctl->mode : -1;
+      S.bcast[1] = ctl->n;
+      S.bcast[2] = ctl->cur;
+      S.bcast[3] = ctl->g;
+      S.bcast[4] = ctl->gen;
+    }
+    __syncthreads();
+    mode = S.bcast[0];
+    if (mode < 0 || mode == GM_DONE) break;
+    seen = S.bcast[4];
+    if (mode == GM_NARROW) {
+      part = me == 0;
+      if (part) engine_net<WG, QCAP, 3, MAXL>(S, D, RV, stop, 0, hi, kp, &ctl->heartbeat);
+      continue;
+    }
+    // ---- one parallel step shared by the first g workgroups
+    const int n = S.bcast[1], cur = S.bcast[2], g = S.bcast[3];
+    part = me < g;
+    if (!part) continue;
+    const int per = (n + g - 1) / g;
+    const int i0 = me * per;
+    const int i1 = i0 + per < n ? i0 + per : n;
+    const gint2 *cq_g = (const gint2 *)(cur ? D.queue1 : D.queue0);
+    gint2 *nq_g = (gint2 *)(cur ? D.queue0 : D.queue1);
+    if (tid == 0) S.cnt[0] = 0;
+    __syncthreads();
+    Ctr<CM_GRID> C;
+    C.agent_top = &st->agent_top;
+    C.name_top = &st->name_top;
+    C.nstuck = &st->n_stuck;
+    C.status = &st->status;
+    C.next = &S.cnt[0];
+    C.spill_next = &ctl->next;
+    for (int base = i0; base < i1; base += WG) {
+      const int i = base + tid;
+      const bool valid = i < i1;
+      const Pair rx = valid ? unpk(*at2((gint2 *)cq_g, (unsigned)i)) : mkpair(0, 0);
+      const v4i ra = *rec(agent, (unsigned)rx.x), rb = *rec(agent, (unsigned)rx.y);
+      int nha, nhb;
+      pass_static<QCAP, MAXL, CM_GRID, false>(valid, rx.x, rx.y, ra.x, rb.x, ra.y, ra.z, rb.y,
+                                              rb.z, D, agent, bind, stuck, RV.rule_of, S.q[0],
+                                              nq_g, C, loops_lane, rc_lane, nha, nhb);
+    }
+    // the workgroup's new active pairs from its LDS tile to the next frontier
+    __syncthreads();
+    const int tile = S.cnt[0] < QCAP ? S.cnt[0] : QCAP;
+    if (tid == 0) S.bcast[5] = tile ? gadd(&ctl->next, tile) : 0;
+    __syncthreads();
+    const int gb = S.bcast[5];
+    bool over = false;
+    for (int k = tid; k < tile; k += WG) {
+      if (gb + k < D.qcap) *at2(nq_g, (unsigned)(gb + k)) = pk(S.q[0][k].x, S.q[0][k].y);
+      else over = true;
+    }
+    if (over) gstore(&st->status, ST_ENOMEM);
+  }
+  // this workgroup's interactions per rule and dropped loops of its shared steps
+  gu64 *per_rule = (gu64 *)D.per_rule;
+  const int lane = __lane_id();
+  if (rc_lane && lane < nr) {
+    __hip_atomic_fetch_add((unsigned long long *)&per_rule[lane], (unsigned long long)rc_lane,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&st->interactions, (unsigned long long)rc_lane, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (loops_lane) gadd(&st->loops, loops_lane);
+}
+#endif  // INET_STATIC_RULES
+
 
 #ifndef __HIPCC_RTC__
 template <int WG, int QCAP, int ENGINE, int MAXL>
 __global__ __launch_bounds__(WG) void k_reduce(const NetDesc *__restrict__ descs,
                                                const int *__restrict__ order, int n_nets,
                                                int *counter, const int *__restrict__ g_rules,
-                                               int ns, int nr, unsigned max_steps, int flags) {
+                                               int ns, int nr, unsigned max_steps, int flags,
+                                               KParams kp) {
   reduce_body<WG, QCAP, ENGINE, MAXL>(descs, order, n_nets, counter, g_rules, ns, nr, max_steps,
-                                      flags);
+                                      flags, kp);
 }
 
-// pointer jumping over one net's cells with the whole grid (single big nets)
-__global__ __launch_bounds__(256) void k_jump_grid(const NetDesc *__restrict__ desc) {
+// pointer jumping over one net's cells with the whole grid (single big nets):
+// rounds over all cells separated by a barrier over the launch, until a round
+// moves nothing (at most 32 rounds); a barrier wait that gives up ends the
+// pass early (the cells then hold partly compressed chains, which read back
+// the same)
+__global__ __launch_bounds__(256) void k_jump_grid(const NetDesc *__restrict__ desc, GridCtl *ctl,
+                                                   unsigned long long timeout) {
+  __shared__ int s_again;
   const NetDesc D = desc[0];
+  // the same decision in every block: nothing writes the state meanwhile
   if (D.st->phase != PHASE_DONE || D.st->status < 0) return;
   const int nn = D.st->name_top;
-  jump_cells((gint *)D.bind, blockIdx.x * 256 + threadIdx.x, nn, gridDim.x * 256);
+  const int G = gridDim.x;
+  gint *const bind = (gint *)D.bind;
+  int seen = 0;
+  for (int round = 0; round < 32; round++) {
+    bool moved = false;
+    for (int x = blockIdx.x * 256 + threadIdx.x; x < nn; x += G * 256) moved |= jump_hop(bind, x);
+    if (__syncthreads_or(moved) && threadIdx.x == 0) gstore(&ctl->moved[round & 1], 1);
+    const bool ok = grid_sync(ctl, G, seen, timeout,
+                              [&] { gstore(&ctl->moved[(round + 1) & 1], 0); });
+    if (threadIdx.x == 0) s_again = ok ? gload(&ctl->moved[round & 1]) : 0;
+    __syncthreads();
+    if (!s_again) break;
+  }
 }
 
 // restore one net to its loaded state with the lanes tid, tid + stride, ...

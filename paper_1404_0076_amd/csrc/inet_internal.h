@@ -101,7 +101,45 @@ struct AdmitRec {
 };
 
 // status codes as seen by the kernels (mirror inet_status)
-enum { ST_OK = 0, ST_STUCK = 1, ST_ENOMEM = -2, ST_ELIMIT = -3, ST_EINTERNAL = -8 };
+enum { ST_OK = 0, ST_STUCK = 1, ST_ENOMEM = -2, ST_ELIMIT = -3, ST_EINTERNAL = -8,
+       ST_ETIMEDOUT = -9 };
+
+// Control block of the multi-workgroup engine of one net (global memory,
+// cleared before each launch).  The launch runs in epochs separated by a
+// barrier: in a NARROW epoch workgroup 0 steps the net alone; in a GRID epoch
+// the g workgroups of lowest logical index share one parallel step.  The
+// last workgroup to arrive decides the next epoch and publishes it by
+// bumping `gen`.  Each group of words sits on its own 128-byte line.
+enum { GM_NARROW = 0, GM_GRID = 1, GM_DONE = 2 };
+struct GridCtl {
+  int32_t arrive;  // arrivals in the current epoch
+  int32_t pad0[31];
+  int32_t gen;        // epoch counter (bumped by the deciding workgroup)
+  int32_t heartbeat;  // bumped by workgroup 0 while it steps alone
+  int32_t pad1[30];
+  int32_t mode;    // GM_* of the current epoch
+  int32_t n;       // active pairs of the current (GRID) step, in queue `cur`
+  int32_t cur;     // queue holding them (0: queue0, 1: queue1)
+  int32_t g;       // participating workgroups (GRID)
+  int32_t target;  // arrivals that end the current epoch
+  uint32_t steps;  // steps done before the current epoch
+  uint32_t stop;   // step budget end (absolute)
+  int32_t moved[2];  // pointer jumping: a cell moved in round r (moved[r & 1])
+  int32_t gave_up;   // a workgroup gave up waiting (sticky)
+  int32_t pad2[22];
+  int32_t next;  // frontier entries appended in the current GRID step
+  int32_t pad3[31];
+};
+
+// tunables of the reduction kernel (by value)
+struct KParams {
+  GridCtl *ctl;         // multi-workgroup engine: its control block (else null)
+  int32_t solo_max;     // one-wave steps while at most this many pairs are active
+  int32_t grid_lo;      // multi-workgroup steps while more than this many are active
+  int32_t grid_hi;      // workgroup 0 hands over once more than this many are active
+  int32_t grid_ppw;     // target active pairs per workgroup in a multi-workgroup step
+  uint64_t timeout;     // give-up of a barrier wait without progress, wall-clock ticks
+};
 
 }  // namespace inet
 

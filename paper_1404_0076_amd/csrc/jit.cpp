@@ -4,8 +4,9 @@
 // templates have been written into it as constant arrays (namespace rt), so
 // each rule's right-hand side becomes straight-line code (engine 3; engine 4
 // is the same code with per-lane atomic reservations).  One code object per
-// (rule table, device architecture, engine) holds the kernel for every engine
-// width; it is built on first use and kept for the process.
+// (rule table, device architecture, engine, engine width) holds the batch
+// kernel and, for engine 3, the multi-workgroup engine of one net; it is
+// built on first use and kept for the process.
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
@@ -31,7 +32,8 @@ namespace {
 
 struct Module {
   hipModule_t mod = nullptr;
-  std::map<int, hipFunction_t> fn;  // by engine width
+  hipFunction_t fn = nullptr;   // the batch kernel
+  hipFunction_t gfn = nullptr;  // the multi-workgroup engine of one net (engine 3)
   bool failed = false;
   std::string log;
 };
@@ -39,9 +41,7 @@ struct Module {
 std::mutex g_mu;
 std::map<std::string, Module> g_mods;
 
-const int kWidths[] = {64, 128, 256, 512, 1024};
-
-std::string source_for(const CompiledRules &R, int engine) {
+std::string source_for(const CompiledRules &R, int engine, int wg) {
   std::ostringstream o;
   o << "#define INET_STATIC_RULES 1\n#include \"inet_internal.h\"\n";
   o << "namespace inet { namespace rt {\n";
@@ -60,13 +60,19 @@ std::string source_for(const CompiledRules &R, int engine) {
   for (int i = 0; i < R.ns; i++) o << (i ? "," : "") << R.arity[i];
   o << "};\n} }\n#include \"device.h\"\n";
   const int maxl = R.max_links <= 4 ? 4 : MAXEQ;
-  for (int wg : kWidths) {
+  {
     const LaunchShape sh = shape_for(wg, engine, R.max_links);
     o << "extern \"C\" __global__ __launch_bounds__(" << wg << ") void inet_static_" << wg
       << "(const inet::NetDesc *__restrict__ d, const int *__restrict__ ord, int n, int *ctr,"
-         " const int *__restrict__ r, int ns, int nr, unsigned ms, int flags) {\n"
+         " const int *__restrict__ r, int ns, int nr, unsigned ms, int flags, inet::KParams kp) {\n"
       << "  inet::reduce_body<" << wg << ", " << sh.qcap << ", " << engine << ", " << maxl
-      << ">(d, ord, n, ctr, r, ns, nr, ms, flags);\n}\n";
+      << ">(d, ord, n, ctr, r, ns, nr, ms, flags, kp);\n}\n";
+    if (engine == 3)
+      o << "extern \"C\" __global__ __launch_bounds__(" << wg << ") void inet_grid_" << wg
+        << "(const inet::NetDesc *__restrict__ d, const int *__restrict__ r, int ns, int nr,"
+           " unsigned ms, int flags, inet::KParams kp) {\n"
+        << "  inet::grid_body<" << wg << ", " << sh.qcap << ", " << maxl
+        << ">(d, r, ns, nr, ms, flags, kp);\n}\n";
   }
   return o.str();
 }
@@ -86,9 +92,9 @@ std::string key_for(const CompiledRules &R, const std::string &arch) {
 }
 
 // compile the specialised engine; code object into *code (no device needed)
-int compile_code(const CompiledRules &R, const std::string &arch, int engine,
+int compile_code(const CompiledRules &R, const std::string &arch, int engine, int wg,
                  std::vector<char> *code, std::string *log_out) {
-  const std::string src = source_for(R, engine);
+  const std::string src = source_for(R, engine, wg);
   if (const char *dump = std::getenv("INET_JIT_DUMP")) {  // inspection aid
     if (FILE *f = std::fopen(dump, "w")) {
       std::fputs(src.c_str(), f);
@@ -125,16 +131,16 @@ int compile_code(const CompiledRules &R, const std::string &arch, int engine,
   return INET_OK;
 }
 
-int build_module(const CompiledRules &R, const std::string &arch, int engine, Module *M) {
+int build_module(const CompiledRules &R, const std::string &arch, int engine, int wg, Module *M) {
   std::vector<char> code;
-  int rc = compile_code(R, arch, engine, &code, &M->log);
+  int rc = compile_code(R, arch, engine, wg, &code, &M->log);
   if (rc) return rc;
   if (hipModuleLoadData(&M->mod, code.data()) != hipSuccess) return INET_EHIP;
-  for (int wg : kWidths) {
-    hipFunction_t f = nullptr;
-    const std::string name = "inet_static_" + std::to_string(wg);
-    if (hipModuleGetFunction(&f, M->mod, name.c_str()) != hipSuccess) return INET_EHIP;
-    M->fn[wg] = f;
+  const std::string name = "inet_static_" + std::to_string(wg);
+  if (hipModuleGetFunction(&M->fn, M->mod, name.c_str()) != hipSuccess) return INET_EHIP;
+  if (engine == 3) {
+    const std::string gname = "inet_grid_" + std::to_string(wg);
+    if (hipModuleGetFunction(&M->gfn, M->mod, gname.c_str()) != hipSuccess) return INET_EHIP;
   }
   return INET_OK;
 }
@@ -142,56 +148,85 @@ int build_module(const CompiledRules &R, const std::string &arch, int engine, Mo
 }  // namespace
 
 // Kernel of engine 3 or 4 for the rule table and engine width (built on first
-// use).
-int jit_function(const CompiledRules &R, int wg, int engine, hipFunction_t *out) {
+// use); with `grid`, the multi-workgroup engine of one net (engine 3 only).
+static int jit_kernel(const CompiledRules &R, int wg, int engine, bool grid, hipFunction_t *out) {
   if (engine != 3 && engine != 4) return INET_EINVAL;
+  if (!shape_supported(wg) || (grid && engine != 3)) return INET_EINVAL;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return INET_EHIP;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return INET_EHIP;
   std::string arch(prop.gcnArchName);
-  const std::string key =
-      key_for(R, arch) + "/" + std::to_string(dev) + "/" + std::to_string(engine);
+  const std::string key = key_for(R, arch) + "/" + std::to_string(dev) + "/" +
+                          std::to_string(engine) + "/" + std::to_string(wg);
   std::lock_guard<std::mutex> lock(g_mu);
   Module &M = g_mods[key];
   if (M.failed) return INET_ENOSYS;
   if (!M.mod) {
-    int rc = build_module(R, arch, engine, &M);
+    int rc = build_module(R, arch, engine, wg, &M);
     if (rc) {
       M.failed = true;
       if (std::getenv("INET_JIT_LOG")) std::fprintf(stderr, "inet jit: %d\n%s\n", rc, M.log.c_str());
       return rc;
     }
   }
-  auto it = M.fn.find(wg);
-  if (it == M.fn.end()) return INET_EINVAL;
-  *out = it->second;
-  return INET_OK;
+  *out = grid ? M.gfn : M.fn;
+  return *out ? INET_OK : INET_EINVAL;
+}
+
+int jit_function(const CompiledRules &R, int wg, int engine, hipFunction_t *out) {
+  return jit_kernel(R, wg, engine, false, out);
 }
 
 int jit_launch(const CompiledRules &R, const LaunchShape &sh, int grid, const NetDesc *d,
                const int32_t *ord, int n, int32_t *ctr, const int32_t *r, uint32_t ms, int flags,
-               hipStream_t s) {
+               const KParams &kp, hipStream_t s) {
   hipFunction_t f = nullptr;
-  int rc = jit_function(R, sh.wg, sh.engine, &f);
+  int rc = jit_kernel(R, sh.wg, sh.engine, false, &f);
   if (rc) return rc;
   int ns = R.ns, nr = R.nr;
+  KParams k = kp;
   void *args[] = {(void *)&d, (void *)&ord, (void *)&n, (void *)&ctr, (void *)&r,
-                  (void *)&ns, (void *)&nr, (void *)&ms, (void *)&flags};
+                  (void *)&ns, (void *)&nr, (void *)&ms, (void *)&flags, (void *)&k};
   const unsigned dyn = (unsigned)(ns * ns + nr * RT_WORDS + ns) * 4;
   if (hipModuleLaunchKernel(f, grid, 1, 1, sh.wg, 1, 1, dyn, s, args, nullptr) != hipSuccess)
     return INET_EHIP;
   return INET_OK;
 }
 
-int jit_occupancy(const CompiledRules &R, const LaunchShape &sh, int *per_cu) {
+int jit_grid_launch(const CompiledRules &R, const LaunchShape &sh, int grid, const NetDesc *d,
+                    const int32_t *r, uint32_t ms, int flags, const KParams &kp, hipStream_t s) {
+  if (sh.engine != 3 || !kp.ctl) return INET_EINVAL;
   hipFunction_t f = nullptr;
-  int rc = jit_function(R, sh.wg, sh.engine, &f);
+  int rc = jit_kernel(R, sh.wg, 3, true, &f);
+  if (rc) return rc;
+  int ns = R.ns, nr = R.nr;
+  KParams k = kp;
+  void *args[] = {(void *)&d, (void *)&r, (void *)&ns, (void *)&nr, (void *)&ms, (void *)&flags,
+                  (void *)&k};
+  const unsigned dyn = (unsigned)(ns * ns + nr * RT_WORDS + ns) * 4;
+  if (hipModuleLaunchKernel(f, grid, 1, 1, sh.wg, 1, 1, dyn, s, args, nullptr) != hipSuccess)
+    return INET_EHIP;
+  return INET_OK;
+}
+
+static int occupancy_of(const CompiledRules &R, const LaunchShape &sh, bool grid, int *per_cu) {
+  hipFunction_t f = nullptr;
+  int rc = jit_kernel(R, sh.wg, sh.engine, grid, &f);
   if (rc) return rc;
   const size_t dyn = (size_t)(R.ns * R.ns + R.nr * RT_WORDS + R.ns) * 4;
   return hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, f, sh.wg, dyn) == hipSuccess
              ? INET_OK
              : INET_EHIP;
+}
+
+int jit_occupancy(const CompiledRules &R, const LaunchShape &sh, int *per_cu) {
+  return occupancy_of(R, sh, false, per_cu);
+}
+
+int jit_grid_occupancy(const CompiledRules &R, const LaunchShape &sh, int *per_cu) {
+  if (sh.engine != 3) return INET_EINVAL;
+  return occupancy_of(R, sh, true, per_cu);
 }
 
 }  // namespace inet
@@ -202,12 +237,13 @@ extern "C" int inet_jit_build(const inet_rules *rules, const char *arch, size_t 
   int rc = inet::compile_rules(rules, &R);
   if (rc) return rc;
   if (!arch) return INET_EINVAL;
-  // both specialised engines (3, then 4); the first failure ends the build
+  // both specialised engines (3, then 4) at the default width (1024 lanes);
+  // the first failure ends the build
   size_t total = 0;
   std::string msg;
   for (int engine = 3; engine <= 4 && rc == INET_OK; engine++) {
     std::vector<char> code;
-    rc = inet::compile_code(R, arch, engine, &code, &msg);
+    rc = inet::compile_code(R, arch, engine, 1024, &code, &msg);
     total += code.size();
   }
   if (log && log_cap) {

@@ -23,17 +23,18 @@ const void *kernel_for(int engine, int maxl) {
 
 template <int WG, int QCAP>
 int launch_t(int engine, int maxl, int grid, const NetDesc *d, const int32_t *ord, int n,
-             int32_t *ctr, const int32_t *r, int ns, int nr, uint32_t ms, int flags, hipStream_t s) {
+             int32_t *ctr, const int32_t *r, int ns, int nr, uint32_t ms, int flags,
+             const KParams &kp, hipStream_t s) {
   const size_t dyn = (size_t)(ns * ns + nr * RT_WORDS + ns) * 4;
   if (engine == 1)
     hipLaunchKernelGGL((k_reduce<WG, QCAP, 1, MAXEQ>), dim3(grid), dim3(WG), dyn, s, d, ord, n, ctr,
-                       r, ns, nr, ms, flags);
+                       r, ns, nr, ms, flags, kp);
   else if (maxl <= 4)
     hipLaunchKernelGGL((k_reduce<WG, QCAP, 2, 4>), dim3(grid), dim3(WG), dyn, s, d, ord, n, ctr, r,
-                       ns, nr, ms, flags);
+                       ns, nr, ms, flags, kp);
   else
     hipLaunchKernelGGL((k_reduce<WG, QCAP, 2, MAXEQ>), dim3(grid), dim3(WG), dyn, s, d, ord, n, ctr,
-                       r, ns, nr, ms, flags);
+                       r, ns, nr, ms, flags, kp);
   return hipGetLastError() == hipSuccess ? INET_OK : INET_EHIP;
 }
 
@@ -66,12 +67,12 @@ LaunchShape shape_for(int wg, int engine, int maxl) {
 
 int launch_reduce(const CompiledRules &R, const LaunchShape &sh, int grid, const NetDesc *d,
                   const int32_t *ord, int n, int32_t *ctr, const int32_t *r, uint32_t ms, int flags,
-                  hipStream_t s) {
-  if (sh.engine >= 3) return jit_launch(R, sh, grid, d, ord, n, ctr, r, ms, flags, s);
+                  const KParams &kp, hipStream_t s) {
+  if (sh.engine >= 3) return jit_launch(R, sh, grid, d, ord, n, ctr, r, ms, flags, kp, s);
   const int ns = R.ns, nr = R.nr;
 #define X(W, Q) \
   if (sh.wg == W && sh.qcap == Q)    \
-    return launch_t<W, Q>(sh.engine, sh.maxl, grid, d, ord, n, ctr, r, ns, nr, ms, flags, s);
+    return launch_t<W, Q>(sh.engine, sh.maxl, grid, d, ord, n, ctr, r, ns, nr, ms, flags, kp, s);
   INET_SHAPES(X)
 #undef X
   return INET_EINVAL;
@@ -110,8 +111,9 @@ int launch_zero(int32_t *p, int n, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? INET_OK : INET_EHIP;
 }
 
-int launch_jump_grid(const NetDesc *d, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_jump_grid, dim3(grid), dim3(256), 0, s, d);
+int launch_jump_grid(const NetDesc *d, GridCtl *ctl, uint64_t timeout, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_jump_grid, dim3(grid), dim3(256), 0, s, d, ctl,
+                     (unsigned long long)timeout);
   return hipGetLastError() == hipSuccess ? INET_OK : INET_EHIP;
 }
 

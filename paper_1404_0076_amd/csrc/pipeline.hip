@@ -17,22 +17,21 @@
 // are never touched: sub and col are left to the read-back (Theorem 1 of
 // Section 2.2).  Allocation of the new agents and names is a prefix sum over
 // the active pairs' needs.  The steps the paper runs with Thrust (remove,
-// sort, reduce_by_key) are rocPRIM's device primitives here; the interaction
-// and the bookkeeping are kernels of this file.  When the loop ends, each
+// sort, reduce_by_key) are the device primitives of primitives.h (prefix sum,
+// compaction, radix sort, reduce by key); the interaction and the bookkeeping
+// are kernels of this file.  When the loop ends, each
 // remaining equation x = t is written into x's name cell and each remaining
 // pair of agents (no rule) into the residual list, which is the state the
 // read-back of the net engines expects.
 #include <hip/hip_runtime.h>
 
-#include <cstring>  // before rocPRIM, whose iterators use memset
-
-#include <rocprim/rocprim.hpp>
-
 #include <algorithm>
+#include <cstring>
 #include <vector>
 
 #include "../../include/inet.h"
 #include "inet_internal.h"
+#include "primitives.h"
 #include "runtime.h"
 
 namespace inet {
@@ -155,13 +154,12 @@ __global__ void k_pp_finish(const u64 *__restrict__ eq, int m, NetDesc D, int *c
   else atomicExch(&ctr[C_NOMEM], 1);
 }
 
-struct NotDummy {
-  __device__ bool operator()(const u64 &e) const { return e != DUMMY; }
-};
-
 // com of two equations sharing their key x: (x, t) and (x, s) give (s, t)
 struct Merge {
   __device__ u64 operator()(const u64 &p, const u64 &q) const { return pk2(hi(q), hi(p)); }
+};
+struct Sum {
+  __device__ u64 operator()(const u64 &p, const u64 &q) const { return p + q; }
 };
 
 // the loop's device arrays, each of `cap` elements (temporary memory: the
@@ -169,11 +167,11 @@ struct Merge {
 struct Buffers {
   u64 *eq = nullptr, *out = nullptr, *tmp = nullptr, *need = nullptr, *incl = nullptr;
   unsigned *key = nullptr, *key2 = nullptr;
-  void *scratch = nullptr;
-  size_t cap = 0, scratch_bytes = 0;
+  prim::Scratch arena;  // the primitives' temporary memory
+  size_t cap = 0;
   void release() {
     for (void *p : {(void *)eq, (void *)out, (void *)tmp, (void *)need, (void *)incl, (void *)key,
-                    (void *)key2, scratch})
+                    (void *)key2, (void *)arena.base})
       if (p) (void)hipFree(p);
     *this = Buffers();
   }
@@ -192,18 +190,8 @@ int ensure(Buffers &B, size_t items, hipStream_t s) {
             hipMalloc(&N.key2, 4 * cap) == hipSuccess;
   if (!ok) { N.release(); return INET_ENOMEM; }
   // temporary storage of the primitives, sized for the largest input
-  size_t b1 = 0, b2 = 0, b3 = 0, b4 = 0;
-  hipError_t e = rocprim::inclusive_scan(nullptr, b1, N.need, N.incl, cap, rocprim::plus<u64>(), s);
-  if (e == hipSuccess)
-    e = rocprim::select(nullptr, b2, N.out, N.tmp, (size_t *)nullptr, cap, NotDummy(), s);
-  if (e == hipSuccess)
-    e = rocprim::radix_sort_pairs(nullptr, b3, N.key, N.key2, N.tmp, N.eq, cap, 0, 32, s);
-  if (e == hipSuccess)
-    e = rocprim::reduce_by_key(nullptr, b4, N.key2, N.eq, cap, N.key, N.tmp, (size_t *)nullptr,
-                               Merge(), rocprim::equal_to<unsigned>(), s);
-  if (e != hipSuccess) { N.release(); return INET_EHIP; }
-  N.scratch_bytes = std::max(std::max(b1, b2), std::max(b3, b4)) + 256;
-  if (hipMalloc(&N.scratch, N.scratch_bytes) != hipSuccess) { N.release(); return INET_ENOMEM; }
+  N.arena.size = prim::scratch_bytes(cap);
+  if (hipMalloc((void **)&N.arena.base, N.arena.size) != hipSuccess) { N.release(); return INET_ENOMEM; }
   if (B.eq && hipMemcpyAsync(N.eq, B.eq, 8 * B.cap, hipMemcpyDeviceToDevice, s) != hipSuccess) {
     N.release();
     return INET_EHIP;
@@ -218,7 +206,7 @@ int grid_of(int m) { return (m + 255) / 256; }
 
 // the paper's loop on one net; its state is left as after a reduction
 int pipeline_net(inet_net *h, int i, hipStream_t s, uint64_t max_iter, Buffers &B, int *d_ctr,
-                 size_t *d_count) {
+                 int64_t *d_count) {
   const CompiledRules &R = h->rules;
   const NetDesc &D = h->descs[i];
   const int ns = R.ns, n_slots = std::max(1, R.max_links);
@@ -241,20 +229,19 @@ int pipeline_net(inet_net *h, int i, hipStream_t s, uint64_t max_iter, Buffers &
       // int: allocation by prefix sum, then n slots per equation
       hipLaunchKernelGGL(k_pp_need, dim3(grid_of(m)), dim3(256), 0, s, B.eq, m, D.agent,
                          h->d_rules, ns, R.nr, B.need);
-      size_t sb = B.scratch_bytes;
-      HIPCHK(rocprim::inclusive_scan(B.scratch, sb, B.need, B.incl, (size_t)m,
-                                     rocprim::plus<u64>(), s));
+      B.arena.reset();
+      if (prim::inclusive_sum<u64>(B.need, B.incl, (size_t)m, B.arena, s)) return INET_EHIP;
       hipLaunchKernelGGL(k_pp_int, dim3(grid_of(m)), dim3(256), 0, s, B.eq, m, B.need, B.incl,
                          h->d_rules, ns, n_slots, D, agent_top, name_top, B.out, d_ctr);
       u64 total = 0;  // what this iteration allocated: agents high, names low
       HIPCHK(hipMemcpyAsync(&total, B.incl + (m - 1), 8, hipMemcpyDeviceToHost, s));
       // filter: drop the dummies
-      sb = B.scratch_bytes;
-      HIPCHK(rocprim::select(B.scratch, sb, B.out, B.tmp, d_count, (size_t)m * n_slots, NotDummy(),
-                             s));
-      size_t sel = 0;
+      B.arena.reset();
+      if (prim::select_not(B.out, B.tmp, (size_t)m * n_slots, DUMMY, d_count, B.arena, s))
+        return INET_EHIP;
+      int64_t sel = 0;
       int ctr[C_WORDS];
-      HIPCHK(hipMemcpyAsync(&sel, d_count, sizeof(size_t), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(&sel, d_count, sizeof(int64_t), hipMemcpyDeviceToHost, s));
       HIPCHK(hipMemcpyAsync(ctr, d_ctr, 4 * C_WORDS, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       if (ctr[C_NOMEM]) { status = INET_ENOMEM; break; }
@@ -270,14 +257,16 @@ int pipeline_net(inet_net *h, int i, hipStream_t s, uint64_t max_iter, Buffers &
     size_t n_com = 0;
     if (m > 1) {
       hipLaunchKernelGGL(k_pp_key, dim3(grid_of(m)), dim3(256), 0, s, B.eq, m, B.key);
-      size_t sb = B.scratch_bytes;
-      HIPCHK(rocprim::radix_sort_pairs(B.scratch, sb, B.key, B.key2, B.eq, B.tmp, (size_t)m, 0, 32,
-                                       s));
-      sb = B.scratch_bytes;
-      HIPCHK(rocprim::reduce_by_key(B.scratch, sb, B.key2, B.tmp, (size_t)m, B.key, B.eq, d_count,
-                                    Merge(), rocprim::equal_to<unsigned>(), s));
-      size_t uniq = 0;
-      HIPCHK(hipMemcpyAsync(&uniq, d_count, sizeof(size_t), hipMemcpyDeviceToHost, s));
+      B.arena.reset();
+      if (prim::radix_sort_pairs<u64>(B.key, B.eq, B.key2, B.tmp, (size_t)m, B.arena, s))
+        return INET_EHIP;
+      B.arena.reset();
+      if (prim::reduce_by_key<u64>(B.key, B.eq, (size_t)m, B.key2, B.tmp, d_count, Merge(),
+                                   B.arena, s))
+        return INET_EHIP;
+      std::swap(B.eq, B.tmp);  // the merged equations
+      int64_t uniq = 0;
+      HIPCHK(hipMemcpyAsync(&uniq, d_count, sizeof(int64_t), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       n_com = (size_t)m - uniq;
       m = (int)uniq;
@@ -326,7 +315,7 @@ extern "C" int inet_reduce_pipeline(inet_net *h, hipStream_t stream, uint64_t ma
   if (max_iterations == 0) max_iterations = ~0ull;
   Buffers B;
   int *d_ctr = nullptr;
-  size_t *d_count = nullptr;
+  int64_t *d_count = nullptr;
   if (hipMalloc(&d_ctr, 4 * C_WORDS) != hipSuccess) return INET_ENOMEM;
   if (hipMalloc(&d_count, 64) != hipSuccess) { (void)hipFree(d_ctr); return INET_ENOMEM; }
   int rc = INET_OK;
@@ -338,4 +327,89 @@ extern "C" int inet_reduce_pipeline(inet_net *h, hipStream_t stream, uint64_t ma
   (void)hipFree(d_count);
   h->results_valid = false;
   return rc;
+}
+
+// ---------------------------------------------------------------------------
+// the primitives on caller arrays (tests)
+
+namespace {
+struct ArenaFor {
+  inet::prim::Scratch S;
+  explicit ArenaFor(size_t n) {
+    S.size = inet::prim::scratch_bytes(n);
+    if (hipMalloc((void **)&S.base, S.size) != hipSuccess) S.base = nullptr;
+  }
+  ~ArenaFor() {
+    if (S.base) (void)hipFree(S.base);
+  }
+};
+
+int count_back(int64_t *d_n, int64_t *n_out, hipStream_t s) {
+  if (hipMemcpyAsync(n_out, d_n, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return INET_EHIP;
+  return INET_OK;
+}
+}  // namespace
+
+extern "C" int inet_prim_scan(const uint64_t *d_in, uint64_t *d_out, int64_t n, hipStream_t s) {
+  if (n < 0 || (n && (!d_in || !d_out))) return INET_EINVAL;
+  ArenaFor A((size_t)n);
+  if (!A.S.base) return INET_ENOMEM;
+  if (inet::prim::inclusive_sum<unsigned long long>((const unsigned long long *)d_in,
+                                                    (unsigned long long *)d_out, (size_t)n, A.S, s))
+    return INET_EHIP;
+  return hipStreamSynchronize(s) == hipSuccess ? INET_OK : INET_EHIP;
+}
+
+extern "C" int inet_prim_select(const uint64_t *d_in, uint64_t *d_out, int64_t n, uint64_t drop,
+                                int64_t *n_out, hipStream_t s) {
+  if (n < 0 || !n_out || (n && (!d_in || !d_out))) return INET_EINVAL;
+  ArenaFor A((size_t)n);
+  int64_t *d_n = nullptr;
+  if (!A.S.base || A.S.take(sizeof(int64_t), (void **)&d_n)) return INET_ENOMEM;
+  if (inet::prim::select_not((const unsigned long long *)d_in, (unsigned long long *)d_out,
+                             (size_t)n, (unsigned long long)drop, d_n, A.S, s))
+    return INET_EHIP;
+  return count_back(d_n, n_out, s);
+}
+
+extern "C" int inet_prim_sort_pairs(uint32_t *d_keys, uint64_t *d_vals, int64_t n, hipStream_t s) {
+  if (n < 0 || (n && (!d_keys || !d_vals))) return INET_EINVAL;
+  if (n <= 1) return INET_OK;
+  ArenaFor A((size_t)n);
+  uint32_t *k2 = nullptr;
+  unsigned long long *v2 = nullptr;
+  if (hipMalloc((void **)&k2, 4 * (size_t)n) != hipSuccess) return INET_ENOMEM;
+  if (hipMalloc((void **)&v2, 8 * (size_t)n) != hipSuccess) {
+    (void)hipFree(k2);
+    return INET_ENOMEM;
+  }
+  int rc = A.S.base ? INET_OK : INET_ENOMEM;
+  if (!rc && inet::prim::radix_sort_pairs<unsigned long long>(
+                 d_keys, (unsigned long long *)d_vals, k2, v2, (size_t)n, A.S, s))
+    rc = INET_EHIP;
+  if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = INET_EHIP;
+  (void)hipFree(k2);
+  (void)hipFree(v2);
+  return rc;
+}
+
+extern "C" int inet_prim_reduce_by_key(const uint32_t *d_keys, const uint64_t *d_vals, int64_t n,
+                                       uint32_t *d_keys_out, uint64_t *d_vals_out, int32_t op,
+                                       int64_t *n_out, hipStream_t s) {
+  if (n < 0 || !n_out || (op != 0 && op != 1) ||
+      (n && (!d_keys || !d_vals || !d_keys_out || !d_vals_out)))
+    return INET_EINVAL;
+  ArenaFor A((size_t)n);
+  int64_t *d_n = nullptr;
+  if (!A.S.base || A.S.take(sizeof(int64_t), (void **)&d_n)) return INET_ENOMEM;
+  int e = op == 0 ? inet::prim::reduce_by_key<unsigned long long>(
+                        d_keys, (const unsigned long long *)d_vals, (size_t)n, d_keys_out,
+                        (unsigned long long *)d_vals_out, d_n, inet::Sum(), A.S, s)
+                  : inet::prim::reduce_by_key<unsigned long long>(
+                        d_keys, (const unsigned long long *)d_vals, (size_t)n, d_keys_out,
+                        (unsigned long long *)d_vals_out, d_n, inet::Merge(), A.S, s);
+  if (e) return INET_EHIP;
+  return count_back(d_n, n_out, s);
 }

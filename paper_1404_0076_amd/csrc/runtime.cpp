@@ -41,7 +41,8 @@ bool plan_net(int64_t n_agents, int64_t n_eqs, int64_t n_names, int64_t agent_ca
 
 size_t global_bytes(const CompiledRules &R, int32_t n_nets, int64_t total_agents, int64_t total_eqs) {
   return al(R.blob.size() * 4) + al(sizeof(NetDesc) * (size_t)n_nets) + al(4 * (size_t)n_nets) +
-         256 + al(sizeof(NetState) * (size_t)n_nets) + al(8 * (size_t)R.nr * (size_t)n_nets + 8) +
+         256 + al(sizeof(GridCtl)) + al(sizeof(NetState) * (size_t)n_nets) +
+         al(8 * (size_t)R.nr * (size_t)n_nets + 8) +
          al(4 * (size_t)total_agents + 4) + al(8 * (size_t)total_agents + 8) +
          al(8 * (size_t)total_eqs + 8);
 }
@@ -117,6 +118,36 @@ LaunchShape effective_shape(const inet_config &cfg, int n_nets, const CompiledRu
   return shape_for(wg, engine, R.max_links);
 }
 
+bool config_valid(const inet_config &c) {
+  if (c.wg_size != 0 && !shape_supported(c.wg_size)) return false;
+  if (c.max_resident < 0 || c.engine < 0 || c.engine > 4) return false;
+  if (c.solo_max < 0 || c.grid < -1 || c.grid_lo < 0 || c.grid_hi < 0 || c.grid_ppw < 0 ||
+      c.timeout_us < 0)
+    return false;
+  return true;
+}
+
+int kparams_for(const inet_config &c, GridCtl *ctl, KParams *kp) {
+  static int rate_khz[64] = {0};  // wall-clock rate per device
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return INET_EHIP;
+  int khz = dev < 64 ? rate_khz[dev] : 0;
+  if (khz <= 0) {
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+      khz = 100000;  // the documented 100 MHz constant clock
+    if (dev < 64) rate_khz[dev] = khz;
+  }
+  *kp = KParams{};
+  kp->ctl = ctl;
+  kp->solo_max = c.solo_max > 0 ? c.solo_max : 64;
+  kp->grid_lo = c.grid_lo > 0 ? c.grid_lo : 1024;
+  kp->grid_hi = std::max(c.grid_hi > 0 ? c.grid_hi : 2048, kp->grid_lo);
+  kp->grid_ppw = c.grid_ppw;
+  const uint64_t us = c.timeout_us > 0 ? (uint64_t)c.timeout_us : 2000000ull;
+  kp->timeout = us * (uint64_t)khz / 1000ull;
+  return INET_OK;
+}
+
 int resident_grid(const LaunchShape &sh, const CompiledRules &R, const inet_config &cfg,
                   int n_nets, int *grid) {
   *grid = 1;
@@ -150,6 +181,7 @@ const char *inet_strerror(int status) {
     case INET_EHIP: return "HIP runtime error";
     case INET_ENOSYS: return "not supported";
     case INET_EINTERNAL: return "internal invariant violated";
+    case INET_ETIMEDOUT: return "a workgroup gave up waiting at a barrier";
     default: return "unknown status";
   }
 }
@@ -226,6 +258,7 @@ int inet_batch_load(const inet_rules *rules, int32_t n_nets, const int32_t *labe
   h->d_descs = (NetDesc *)take(sizeof(NetDesc) * (size_t)n_nets);
   h->d_order = (int32_t *)take(4 * (size_t)n_nets);
   h->d_counter = (int32_t *)take(256);
+  h->d_grid = (GridCtl *)take(sizeof(GridCtl));
   h->d_states = (NetState *)take(sizeof(NetState) * (size_t)n_nets);
   h->d_per_rule = (unsigned long long *)take(8 * (size_t)R.nr * (size_t)n_nets + 8);
   h->d_init_label = (int32_t *)take(4 * (size_t)A + 4);
@@ -293,9 +326,7 @@ int inet_load(const inet_rules *rules, const int32_t *label, const int32_t *port
 }
 
 int inet_set_config(inet_net *h, const inet_config *cfg) {
-  if (!h || !cfg) return INET_EINVAL;
-  if (cfg->wg_size != 0 && !shape_supported(cfg->wg_size)) return INET_EINVAL;
-  if (cfg->max_resident < 0 || cfg->engine < 0 || cfg->engine > 4) return INET_EINVAL;
+  if (!h || !cfg || !config_valid(*cfg)) return INET_EINVAL;
   h->cfg = *cfg;
   return INET_OK;
 }
@@ -320,27 +351,58 @@ int inet_set_order(inet_net *h, const int32_t *order) {
   return INET_OK;
 }
 
+// workgroups of the multi-workgroup engine for a handle's single net (0: the
+// net runs on one workgroup)
+static int grid_workgroups(const inet_net *h, const LaunchShape &sh, int *G) {
+  *G = 0;
+  if (h->n_nets != 1 || sh.engine != 3 || h->cfg.grid < 0) return INET_OK;
+  int per_cu = 0, n_cu = 0, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return INET_EHIP;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return INET_EHIP;
+  int rc = jit_grid_occupancy(h->rules, sh, &per_cu);
+  if (rc) return rc;
+  // every workgroup must be resident at once (they wait for each other)
+  int g = std::max(1, per_cu) * std::max(1, n_cu);
+  if (h->cfg.grid > 0) g = std::min(g, h->cfg.grid);
+  *G = g >= 2 ? g : 0;
+  return INET_OK;
+}
+
 // the reduction of every net of a handle: clear the net counter, the
-// persistent launch, the pointer-jumping pass (events around it if timed)
+// persistent launch (the multi-workgroup engine for a single net), the
+// pointer-jumping pass (events around the launch if timed)
 static int enqueue_reduce(inet_net *h, hipStream_t stream, uint64_t max_steps, bool timed) {
   const LaunchShape sh = shape_of(h);
   const uint32_t ms = (max_steps == 0 || max_steps > kStepsPerLaunch) ? kStepsPerLaunch : (uint32_t)max_steps;
-  int grid = 1;
+  int grid = 1, G = 0;
   int rc = resident_grid(sh, h->rules, h->cfg, h->n_nets, &grid);
+  if (!rc) rc = grid_workgroups(h, sh, &G);
   if (rc) return rc;
-  rc = launch_zero(h->d_counter, 1, stream);
+  KParams kp;
+  rc = kparams_for(h->cfg, G ? h->d_grid : nullptr, &kp);
+  if (!rc) rc = launch_zero(h->d_counter, 1, stream);
+  if (!rc && G) rc = launch_zero((int32_t *)h->d_grid, (int)(sizeof(GridCtl) / 4), stream);
   if (rc) return rc;
   if (timed) HIPCHK(hipEventRecord(h->ev0, stream));
   const bool jump = h->cfg.jump != 0;
   const int flags = (jump && h->n_nets > 1) ? FLAG_JUMP : 0;
-  rc = launch_reduce(h->rules, sh, grid, h->d_descs, h->d_order, h->n_nets, h->d_counter,
-                     h->d_rules, ms, flags, stream);
+  if (G)
+    rc = jit_grid_launch(h->rules, sh, G, h->d_descs, h->d_rules, ms, 0, kp, stream);
+  else
+    rc = launch_reduce(h->rules, sh, grid, h->d_descs, h->d_order, h->n_nets, h->d_counter,
+                       h->d_rules, ms, flags, kp, stream);
   if (rc) return rc;
+  if (timed) HIPCHK(hipEventRecord(h->ev1, stream));
   if (jump && h->n_nets == 1) {
-    rc = launch_jump_grid(h->d_descs, 1024, stream);
+    int n_cu = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return INET_EHIP;
+    rc = launch_zero((int32_t *)h->d_grid, (int)(sizeof(GridCtl) / 4), stream);
+    if (!rc) rc = launch_jump_grid(h->d_descs, h->d_grid, kp.timeout, std::max(1, n_cu), stream);
     if (rc) return rc;
   }
-  if (timed) HIPCHK(hipEventRecord(h->ev1, stream));
   return INET_OK;
 }
 
@@ -464,6 +526,17 @@ int inet_per_rule(inet_net *h, int32_t net, uint64_t *counts, int32_t cap) {
   if (h->rules.nr == 0) return INET_OK;
   HIPCHK(hipMemcpy(counts, h->d_per_rule + (size_t)net * h->rules.nr, 8 * (size_t)h->rules.nr,
                    hipMemcpyDeviceToHost));
+  return INET_OK;
+}
+
+int inet_cells(inet_net *h, int32_t net, int32_t *buf, int64_t cap, int64_t *len) {
+  if (!h || net < 0 || net >= h->n_nets || !len) return INET_EINVAL;
+  if (!h->results_valid) return INET_EINVAL;
+  const NetState &s = h->states[net];
+  const int64_t n = std::max<int32_t>(0, s.name_top);
+  *len = n;
+  if (!buf || cap < n) return INET_ERANGE;
+  if (n) HIPCHK(hipMemcpy(buf, h->descs[net].bind, 4 * (size_t)n, hipMemcpyDeviceToHost));
   return INET_OK;
 }
 

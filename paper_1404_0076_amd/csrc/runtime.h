@@ -39,15 +39,25 @@ int launch_admit(const AdmitRec *d_recs, int n, NetDesc *d_descs, int nr, hipStr
 int launch_zero(int32_t *p, int n, hipStream_t s);
 int launch_reduce(const CompiledRules &R, const LaunchShape &shape, int grid,
                   const NetDesc *d_descs, const int32_t *d_order, int n_nets, int32_t *d_counter,
-                  const int32_t *d_rules, uint32_t max_steps, int flags, hipStream_t s);
-int launch_jump_grid(const NetDesc *d_desc, int grid, hipStream_t s);
+                  const int32_t *d_rules, uint32_t max_steps, int flags, const KParams &kp,
+                  hipStream_t s);
+int launch_jump_grid(const NetDesc *d_desc, GridCtl *ctl, uint64_t timeout, int grid,
+                     hipStream_t s);
 int max_resident(const CompiledRules &R, const LaunchShape &shape, int *per_cu, int *n_cu);
 // engines 3 and 4: the rule table compiled into the kernel at load time (jit.cpp)
 int jit_function(const CompiledRules &R, int wg, int engine, hipFunction_t *out);
 int jit_launch(const CompiledRules &R, const LaunchShape &sh, int grid, const NetDesc *d,
                const int32_t *ord, int n, int32_t *ctr, const int32_t *r, uint32_t ms, int flags,
-               hipStream_t s);
+               const KParams &kp, hipStream_t s);
 int jit_occupancy(const CompiledRules &R, const LaunchShape &sh, int *per_cu);
+// the multi-workgroup engine of one net (engine 3): kernel, launch, occupancy
+int jit_grid_launch(const CompiledRules &R, const LaunchShape &sh, int grid, const NetDesc *d,
+                    const int32_t *r, uint32_t ms, int flags, const KParams &kp, hipStream_t s);
+int jit_grid_occupancy(const CompiledRules &R, const LaunchShape &sh, int *per_cu);
+// configuration checks and the kernel tunables it selects (ctl: the
+// multi-workgroup control block, or null)
+bool config_valid(const inet_config &c);
+int kparams_for(const inet_config &c, GridCtl *ctl, KParams *kp);
 bool shape_supported(int wg);
 LaunchShape shape_for(int wg, int engine, int maxl);
 
@@ -102,6 +112,7 @@ struct inet_net {
   std::vector<int64_t> agent_off, eq_off;
   std::vector<int32_t> n_names;
   std::vector<std::vector<int32_t>> iface; // interface name ids per net
+  inet::GridCtl *d_grid = nullptr;        // multi-workgroup control block (one net)
   inet::NetState *d_states = nullptr;     // [n_nets], contiguous
   unsigned long long *d_per_rule = nullptr; // [n_nets][nr], contiguous
   std::vector<inet::NetState> states;     // from the last inet_results

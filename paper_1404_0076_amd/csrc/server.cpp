@@ -151,9 +151,7 @@ int inet_server_create(const inet_rules *rules, int32_t max_slots, void *dev, si
 }
 
 int inet_server_set_config(inet_server *s, const inet_config *cfg) {
-  if (!s || !cfg) return INET_EINVAL;
-  if (cfg->wg_size != 0 && !shape_supported(cfg->wg_size)) return INET_EINVAL;
-  if (cfg->max_resident < 0 || cfg->engine < 0 || cfg->engine > 4) return INET_EINVAL;
+  if (!s || !cfg || !config_valid(*cfg)) return INET_EINVAL;
   s->cfg = *cfg;
   return INET_OK;
 }
@@ -249,8 +247,11 @@ int inet_server_step(inet_server *s, hipStream_t stream, uint32_t max_steps) {
   if (rc) return rc;
   rc = launch_zero(s->d_counter, 1, stream);
   if (rc) return rc;
+  KParams kp;
+  rc = kparams_for(cfg, nullptr, &kp);
+  if (rc) return rc;
   rc = launch_reduce(s->rules, sh, grid, s->d_descs, s->d_order, n, s->d_counter, s->d_rules,
-                     max_steps, s->cfg.jump ? FLAG_JUMP : 0, stream);
+                     max_steps, s->cfg.jump ? FLAG_JUMP : 0, kp, stream);
   if (rc) return rc;
   s->round_in_flight = true;
   return INET_OK;
@@ -564,8 +565,10 @@ int inet_server_run(inet_server *s, int32_t n_pool, const int32_t *label, const 
     int grid = 1;
     rc = resident_grid(sh, R, cfg, n, &grid);
     if (!rc) rc = launch_zero(s->d_counter, 1, stream);
+    KParams kp;
+    if (!rc) rc = kparams_for(cfg, nullptr, &kp);
     if (!rc) rc = launch_reduce(R, sh, grid, s->d_descs, s->d_order, n, s->d_counter, s->d_rules,
-                                round_steps, s->cfg.jump ? FLAG_JUMP : 0, stream);
+                                round_steps, s->cfg.jump ? FLAG_JUMP : 0, kp, stream);
     if (rc) break;
     if (hipMemcpyAsync(h_states, s->d_states, sizeof(NetState) * (size_t)M, hipMemcpyDeviceToHost,
                        stream) != hipSuccess) { rc = INET_EHIP; break; }

@@ -74,3 +74,72 @@ def test_batch_and_reset():
         for i in range(len(batch)):
             assert_same((rs[i], h.readback(i), h.per_rule(i)), refs[i], f"net {i} rep {rep}")
     h.free()
+
+
+# ---------------------------------------------------------------------------
+# the ablation's own device primitives against numpy
+
+
+def test_reduce_by_key_paper_example():
+    # Section 3.5: reduce by key on {2,0,3,3,3,7,5,5} with addition as the
+    # fold and equality of neighbours as the predicate gives {2,0,9,7,10}
+    import torch
+    x = [2, 0, 3, 3, 3, 7, 5, 5]
+    keys = torch.tensor(x, dtype=torch.int32, device="cuda")
+    vals = torch.tensor(x, dtype=torch.int64, device="cuda")
+    ko, vo = P.prim.reduce_by_key(keys, vals, op=0)
+    assert vo.cpu().tolist() == [2, 0, 9, 7, 10]
+    assert ko.cpu().tolist() == [2, 0, 3, 7, 5]
+
+
+def _runs(keys):
+    """numpy reference: start index of every run of equal adjacent keys"""
+    k = np.asarray(keys)
+    return np.flatnonzero(np.r_[True, k[1:] != k[:-1]]) if len(k) else np.zeros(0, np.int64)
+
+
+@pytest.mark.parametrize("n", [0, 1, 7, 2047, 2048, 2049, 100_003, 3_000_001])
+def test_primitives_match_numpy(n):
+    import torch
+    rng = np.random.Generator(np.random.PCG64(n + 5))
+    say("primitives", n)
+    # inclusive sum (uint64, wrapping)
+    x = rng.integers(0, 1 << 62, n, dtype=np.int64)
+    got = P.prim.scan(torch.from_numpy(x).cuda()).cpu().numpy().view(np.uint64)
+    assert np.array_equal(got, np.cumsum(x.view(np.uint64), dtype=np.uint64))
+    # compaction of everything but the dummy ~0
+    y = rng.integers(0, 50, n, dtype=np.int64)
+    y[rng.random(n) < 0.4] = -1
+    got = P.prim.select(torch.from_numpy(y).cuda(), -1).cpu().numpy()
+    assert np.array_equal(got, y[y != -1])
+    # stable sort by 32-bit key (few distinct keys, high bits set, values record the input order)
+    keys = rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)
+    keys[rng.random(n) < 0.5] = 0x80000003
+    vals = np.arange(n, dtype=np.int64)
+    kt, vt = torch.from_numpy(keys.view(np.int32)).cuda(), torch.from_numpy(vals).cuda()
+    P.prim.sort_pairs(kt, vt)
+    order = np.argsort(keys, kind="stable")
+    assert np.array_equal(kt.cpu().numpy().view(np.uint32), keys[order])
+    assert np.array_equal(vt.cpu().numpy(), vals[order])
+    # reduce by key: runs of a sorted key array folded by sum
+    rk = np.sort(rng.integers(0, max(1, n // 3 + 1), n)).astype(np.int32)
+    rv = rng.integers(0, 1000, n, dtype=np.int64)
+    ko, vo = P.prim.reduce_by_key(torch.from_numpy(rk).cuda(), torch.from_numpy(rv).cuda(), op=0)
+    heads = _runs(rk)
+    assert np.array_equal(ko.cpu().numpy(), rk[heads])
+    assert np.array_equal(vo.cpu().numpy(), np.add.reduceat(rv, heads) if n else rv[:0])
+
+
+def test_reduce_by_key_merges_equations():
+    # op 1: (x, t) and (x, s) sharing the variable x give the equation (s, t)
+    import torch
+    def eq(l, r):
+        return (l & 0xFFFFFFFF) | ((r & 0xFFFFFFFF) << 32)
+    keys = torch.tensor([4, 4, 9, 11, 11], dtype=torch.int32, device="cuda")
+    vals = torch.tensor([eq(-5, 17), eq(-5, 23), eq(-10, 3), eq(-12, -3), eq(-12, 40)],
+                        dtype=torch.int64, device="cuda")
+    ko, vo = P.prim.reduce_by_key(keys, vals, op=1)
+    got = [(int(v) & 0xFFFFFFFF, (int(v) >> 32) & 0xFFFFFFFF) for v in vo.cpu().numpy().view(np.uint64)]
+    to_i = lambda u: u - (1 << 32) if u >= 1 << 31 else u  # noqa: E731
+    assert ko.cpu().tolist() == [4, 9, 11]
+    assert [(to_i(a), to_i(b)) for a, b in got] == [(23, 17), (-10, 3), (40, -3)]
