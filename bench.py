@@ -254,15 +254,16 @@ def bench_serve(args, P, R, nets, torch, pool_ref=None, pool=None):
     print(json.dumps(out), flush=True)
 
 
-def time_single(P, R, net, wg=1024, reps=3, engine=0):
+def time_single(P, R, net, wg=1024, reps=3, engine=0, **cfg):
     """The plain single-net evaluator on one net: exact capacities from a
     sizing pass, then ``reps`` timed restore + reduce runs.  Returns
     interactions/s over the wall time, the reduce kernel's mean time (HIP
-    events on the launch stream) and the algorithmic-byte roofline fraction."""
+    events on the launch stream) and the algorithmic-byte roofline fraction.
+    ``cfg``: further launch tunables (the multi-workgroup engine's thresholds)."""
     import torch
     ua, un, st, it = size_batch(P, R, [net], wg, engine)
     hs = P.batch_load(R, [net], agent_caps=ua + 64, name_caps=un + 64)
-    hs.set_config(wg_size=wg, engine=engine)
+    hs.set_config(wg_size=wg, engine=engine, **cfg)
     hs.reset(); hs.reduce_async(); torch.cuda.synchronize()
     kms = []
     t1 = time.perf_counter()
@@ -276,10 +277,12 @@ def time_single(P, R, net, wg=1024, reps=3, engine=0):
     assert rs[0].interactions == int(it[0]), "interaction count changed between runs"
     alg = float(np.dot(hs.per_rule(0).astype(np.float64), hs.rule_bytes().astype(np.float64)))
     kmean = float(np.mean(kms))
-    cfg = hs.get_config()
+    used = hs.get_config()
     hs.free()
     return {"value": float(it[0]) / dt, "ms": dt * 1000, "kernel_ms": kmean, "steps": int(st[0]),
-            "interactions": int(it[0]), "wg_size": cfg["wg_size"], "engine": cfg["engine"],
+            "interactions": int(it[0]), "wg_size": used["wg_size"], "engine": used["engine"],
+            "max_frontier": int(rs[0].max_frontier),
+            "config": {k: used[k] for k in P.CONFIG_KEYS if used[k]},
             "roofline_frac": alg / (kmean * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
@@ -344,7 +347,10 @@ def main():
                     help="0 default, 1 interpreter, 2 rule-uniform, 3 rules compiled in at load time, "
                          "4 the same with per-lane atomic append")
     ap.add_argument("--autotune", action="store_true",
-                    help="pick engine width and variant with the autotuner (cached)")
+                    help="tune the launch configuration now (cached) instead of reading the "
+                         "tuned table (paper_1404_0076_amd/tuned.json)")
+    ap.add_argument("--no-tuned", action="store_true",
+                    help="use the library defaults, not the tuned table")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true",
@@ -448,16 +454,28 @@ def main():
     used_a, used_n, steps, inter = size_batch(P, R, net_list, wg, args.engine)
     order = np.argsort(-steps, kind="stable").astype(np.int32)  # longest critical path first
     engine = args.engine
-    if args.autotune:
+    extra = {}  # further tunables (LDS tile, one-wave threshold, multi-workgroup engine)
+    tuned = None
+    if not (args.wg or args.engine or args.no_tuned) or args.autotune:
+        # the launch configuration the autotuner picked for this workload on
+        # this device: from the committed table, or tuned now (--autotune)
         from paper_1404_0076_amd import autotune
-        best = autotune.tune(R, net_list, used_a + 64, used_n + 64, order=order)
-        wg, engine = best["wg_size"], best["engine"]
-        args.max_resident = best["max_resident"]
-        log(f"autotune: wg {wg} engine {engine} max_resident {args.max_resident}")
+        space = autotune.BATCH_SPACE if len(net_list) > 1 else autotune.SINGLE_SPACE
+        best = (autotune.tune(R, net_list, used_a + 64, used_n + 64, order=order, space=space)
+                if args.autotune else autotune.lookup(net_list, space))
+        if best:
+            tuned = dict(best["config"])
+            cfg = dict(tuned)
+            wg = cfg.pop("wg_size", wg) or wg
+            engine = cfg.pop("engine", engine)
+            if "max_resident" in cfg:
+                args.max_resident = cfg.pop("max_resident")
+            extra = cfg
+            log(f"tuned: {tuned}")
     if args.pipeline:
         return bench_pipeline(args, P, R, net_list, workload, used_a, used_n, inter, steps, torch)
     h = P.batch_load(R, net_list, agent_caps=used_a + 64, name_caps=used_n + 64)
-    h.set_config(wg_size=wg, engine=engine, max_resident=args.max_resident)
+    h.set_config(wg_size=wg, engine=engine, max_resident=args.max_resident, **extra)
     h.set_order(order)
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
@@ -500,7 +518,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic", "config": dict(workload, wg_size=wg, engine=h.get_config()["engine"],
                                             max_resident=args.max_resident,
-                                            interactions_per_step=total),
+                                            interactions_per_step=total,
+                                            tuned=tuned is not None,
+                                            **{k: v for k, v in extra.items() if v}),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": counter_traffic(wkey),
@@ -535,8 +555,15 @@ def main():
             if what is None:
                 what = f"Mul(S^{net.meta['a']} Z, S^{net.meta['b']} Z), seed 0"
             log(f"single net {key}")
-            rec = time_single(P, R, net)
+            cfg = {}
+            if not args.no_tuned:
+                from paper_1404_0076_amd import autotune
+                best = autotune.lookup([net], autotune.SINGLE_SPACE)
+                cfg = dict(best["config"]) if best else {}
+            wg1 = cfg.pop("wg_size", 1024) or 1024
+            rec = time_single(P, R, net, wg=wg1, **cfg)
             rec["workload"] = what
+            rec["tuned"] = bool(cfg)
             singles[key] = rec
         out["single_net_configs"] = singles
         out["single_net"] = dict(singles["mul"])

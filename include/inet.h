@@ -159,6 +159,11 @@ typedef struct {
                                progress of the others (INET_ETIMEDOUT for the
                                engine; the jumping pass just ends early);
                                0: 2 s                                        */
+  int32_t qcap;             /* engines 3 and 4: pairs per buffer of the LDS
+                               frontier tile (a power of two, 64..8192; the
+                               rest of a frontier lives in the net's global
+                               queue); 0: by width, 512 for 64 lanes, 1024
+                               for 128 and 256, 2048 for 512, 4096 for 1024 */
 } inet_config;
 
 typedef struct inet_net inet_net;

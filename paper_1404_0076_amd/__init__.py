@@ -59,12 +59,13 @@ class _Config(ctypes.Structure):
                 ("max_resident", ctypes.c_int32), ("engine", ctypes.c_int32),
                 ("solo_max", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("grid_lo", ctypes.c_int32), ("grid_hi", ctypes.c_int32),
-                ("grid_ppw", ctypes.c_int32), ("timeout_us", ctypes.c_int32)]
+                ("grid_ppw", ctypes.c_int32), ("timeout_us", ctypes.c_int32),
+                ("qcap", ctypes.c_int32)]
 
 
 # tunables of inet_config beyond wg_size / jump / max_resident / engine (all
 # 0 = the library's default; grid -1 keeps a single net on one workgroup)
-CONFIG_KEYS = ("solo_max", "grid", "grid_lo", "grid_hi", "grid_ppw", "timeout_us")
+CONFIG_KEYS = ("solo_max", "grid", "grid_lo", "grid_hi", "grid_ppw", "timeout_us", "qcap")
 
 
 def _config(wg_size, jump, max_resident, engine, extra) -> "_Config":

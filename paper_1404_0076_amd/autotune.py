@@ -1,31 +1,53 @@
 """Launch-shape autotuner for the net engines.
 
-For a given workload (a list of nets), times the batched reduction for each
-engine width (lanes per net engine, which also fixes the LDS frontier tile),
-each engine variant and a few caps on resident engines, and keeps the fastest.
-Results are cached in a JSON file keyed by the device name and a signature of
-the workload, so a tuned configuration is reused across runs.
+For a given workload (a list of nets, reduced by one launch), searches the
+launch configuration one knob at a time (coordinate descent from the library
+defaults, in the order of the space: each value of a knob is timed with the
+others held, the fastest kept): engine width (lanes per net engine), engine
+variant, cap on resident engines, LDS frontier tile, one-wave threshold, and
+for a single net the multi-workgroup engine's thresholds.  Results are cached
+in a JSON file keyed by the device name, a signature of the workload and the
+searched space, so a tuned configuration is reused across runs;
+``python -m paper_1404_0076_amd.autotune`` writes the tuned table for the
+benchmark workloads (``TUNED``), which ``bench.py`` reads.
 """
 from __future__ import annotations
 
+import argparse
 import hashlib
 import json
 import os
 import time
-from typing import Dict, Optional, Sequence
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
 from . import batch_load
 
-CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "autotune_cache.json")
+TUNED = os.path.join(HERE, "tuned.json")
+
+# the searched knobs, in search order (inet_config fields; 0 = library default)
+BATCH_SPACE: List[Tuple[str, Tuple[int, ...]]] = [
+    ("wg_size", (1024, 512, 256, 64)),
+    ("engine", (3, 4, 2)),
+    ("max_resident", (0, 256, 128, 64)),
+    ("qcap", (0, 1024, 2048, 8192)),
+    ("solo_max", (64, 32, 128, 256)),
+]
+SINGLE_SPACE: List[Tuple[str, Tuple[int, ...]]] = [
+    ("wg_size", (1024, 512, 256)),
+    ("grid", (0, -1, 64, 32)),
+    ("grid_hi", (2048, 1024, 4096, 8192)),
+    ("grid_lo", (1024, 512, 256, 2048)),
+    ("grid_ppw", (0, 256, 512, 2048)),
+    ("qcap", (0, 2048, 8192)),
+    ("solo_max", (64, 32, 128)),
+]
+# kept for callers of the earlier grid search
 WIDTHS = (64, 128, 256, 512, 1024)
-ENGINES = (2, 3, 4)  # rule-uniform, rules compiled in, and that with atomic append
-# (engine 1 is never faster)
-# caps on resident engines: as many as fit, one per compute unit, or fewer
-# (a batch whose time is one net's critical path runs that path a little
-# faster with fewer engines beside it, as long as the others still finish
-# within it)
+ENGINES = (2, 3, 4)
 RESIDENTS = (0, 64, 128, 256)
 
 
@@ -37,6 +59,10 @@ def workload_signature(net_list: Sequence) -> str:
         h.update(np.ascontiguousarray(n.eq_lhs).tobytes())
         h.update(np.ascontiguousarray(n.eq_rhs).tobytes())
     return h.hexdigest()[:16]
+
+
+def space_signature(space) -> str:
+    return ";".join(f"{k}={'-'.join(map(str, v))}" for k, v in space)
 
 
 def _time(h, reps: int) -> float:
@@ -52,42 +78,120 @@ def _time(h, reps: int) -> float:
     return (time.perf_counter() - t0) / reps
 
 
-def tune(rules, net_list: Sequence, agent_caps, name_caps, order=None, reps: int = 2,
-         widths=WIDTHS, engines=ENGINES, residents=RESIDENTS, cache: Optional[str] = CACHE,
-         verbose: bool = False) -> Dict:
-    """Best {"wg_size", "engine", "max_resident", "seconds"} for this workload."""
+def _valid(h, cfg) -> bool:
+    """The configuration is accepted and its results are complete."""
+    from . import InetError
+    try:
+        h.set_config(**cfg)
+        h.reset()
+        rs = h.reduce()
+    except InetError:
+        return False
+    return all(r.status >= 0 for r in rs)
+
+
+def _load_table(path):
+    if path and os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def _store(path, key, value):
+    table = _load_table(path)
+    table[key] = value
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def key_for(net_list, space) -> str:
     import torch
     dev = torch.cuda.get_device_name(0)
-    key = (f"{dev}/{workload_signature(net_list)}/{len(net_list)}/"
-           f"{'-'.join(map(str, widths))}/{'-'.join(map(str, engines))}/{'-'.join(map(str, residents))}")
-    if cache and os.path.exists(cache):
-        with open(cache) as f:
-            table = json.load(f)
-        if key in table:
-            return table[key]
-    else:
-        table = {}
+    return f"{dev}/{workload_signature(net_list)}/{len(net_list)}/{space_signature(space)}"
+
+
+def lookup(net_list, space, path: str = TUNED) -> Optional[Dict]:
+    """The tuned entry for this workload and space on this device, if any."""
+    return _load_table(path).get(key_for(net_list, space))
+
+
+def tune(rules, net_list: Sequence, agent_caps, name_caps, order=None, reps: int = 2,
+         space=None, cache: Optional[str] = CACHE, verbose: bool = False) -> Dict:
+    """Best configuration for this workload: {"config": {...}, "seconds",
+    "trials"}; ``config`` holds every searched knob (set_config keywords)."""
+    if space is None:
+        space = BATCH_SPACE if len(net_list) > 1 else SINGLE_SPACE
+    key = key_for(net_list, space)
+    if cache:
+        hit = _load_table(cache).get(key)
+        if hit:
+            return hit
     h = batch_load(rules, net_list, agent_caps=agent_caps, name_caps=name_caps)
     if order is not None:
         h.set_order(order)
-    best = None
+    cur = {k: vals[0] for k, vals in space}
     trials = []
-    for wg in widths:
-        for eng in engines:
-            for res in residents:
-                h.set_config(wg_size=wg, engine=eng, max_resident=res)
+    best_t = None
+    for k, vals in space:
+        best_v = cur[k]
+        for v in vals:
+            cfg = dict(cur, **{k: v})
+            if any(t["config"] == cfg for t in trials):
+                t = next(t["seconds"] for t in trials if t["config"] == cfg)
+            elif not _valid(h, cfg):
+                continue
+            else:
                 t = _time(h, reps)
-                trials.append({"wg_size": wg, "engine": eng, "max_resident": res, "seconds": t})
+                trials.append({"config": cfg, "seconds": t})
                 if verbose:
                     print("autotune", trials[-1], flush=True)
-                if best is None or t < best["seconds"]:
-                    best = dict(trials[-1])
+            if best_t is None or t < best_t:
+                best_t, best_v = t, v
+        cur[k] = best_v
     h.free()
-    best["trials"] = trials
+    best = {"config": cur, "seconds": best_t, "trials": trials}
     if cache:
-        table[key] = best
-        tmp = cache + ".tmp"
-        with open(tmp, "w") as f:
-            json.dump(table, f, indent=1)
-        os.replace(tmp, cache)
+        _store(cache, key, best)
     return best
+
+
+def main():
+    """Tune the benchmark's workloads on this GPU and write TUNED."""
+    import sys
+    sys.path.insert(0, os.path.dirname(HERE))
+    import torch
+    import bench
+    import paper_1404_0076_amd as P
+    from . import nets
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=TUNED)
+    ap.add_argument("--only", default="", help="comma-separated workload names")
+    ap.add_argument("--reps", type=int, default=2)
+    args = ap.parse_args()
+    torch.cuda.set_device(0)
+    A = nets.arith_rules()
+    work = {"batch": (A, nets.config4_batch(seed=0)),
+            "addtree": (A, [nets.config1_add_tree(0)]),
+            "mul": (A, [nets.config2_mul(0)]),
+            "fib27": (A, [nets.config3_fib(27)]),
+            "algae27": (nets.algae_rules(), [nets.algae_net(27)]),
+            "ackermann": (nets.ackermann_rules(), [nets.ackermann_net(3, 7)])}
+    only = [w for w in args.only.split(",") if w]
+    for name, (R, net_list) in work.items():
+        if only and name not in only:
+            continue
+        space = BATCH_SPACE if len(net_list) > 1 else SINGLE_SPACE
+        print("tuning", name, flush=True)
+        ua, un, steps, _ = bench.size_batch(P, R, net_list, 1024)
+        order = np.argsort(-steps, kind="stable").astype(np.int32)
+        best = tune(R, net_list, ua + 64, un + 64, order=order, reps=args.reps, space=space,
+                    cache=None, verbose=True)
+        best["workload"] = name
+        _store(args.out, key_for(net_list, space), best)
+        print("tuned", name, best["config"], best["seconds"], flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -25,10 +25,12 @@ struct Heap {
   const int32_t *label, *p0, *p1, *bind;
   int64_t n_agents, n_cells;
   const int32_t *arity;
+  int32_t n_symbols;
 };
 
 // Writes T(ref).  canon == nullptr: names are written as -1 (erased form).
-// Returns false if the walk exceeds the heap (a cycle through the cells).
+// Returns false if the walk exceeds the heap (a cycle through the cells) or
+// meets a reference or label out of range.
 bool emit(const Heap &H, int32_t ref, std::vector<int32_t> *canon, int32_t *next,
           std::vector<int32_t> &out, std::vector<int32_t> &stk, int64_t budget) {
   stk.clear();
@@ -57,6 +59,7 @@ bool emit(const Heap &H, int32_t ref, std::vector<int32_t> *canon, int32_t *next
     }
     if (r >= H.n_agents) return false;
     const int32_t L = H.label[r];
+    if (L < 0 || L >= H.n_symbols) return false;
     out.push_back(L);
     const int ar = H.arity[L];
     if (ar > 1) stk.push_back(H.p1[r]);
@@ -78,7 +81,7 @@ int canonical_stream(const CompiledRules &R, const int32_t *label, const int32_t
                      const int32_t *p1, int64_t n_agents, const int32_t *bind, int64_t n_cells,
                      const std::vector<int32_t> &iface, const std::vector<int2> &stuck,
                      std::vector<int32_t> *out) {
-  Heap H{label, p0, p1, bind, n_agents, n_cells, R.arity.data()};
+  Heap H{label, p0, p1, bind, n_agents, n_cells, R.arity.data(), R.ns};
   const int64_t budget = 2 * (n_agents + n_cells) + 16;
   std::vector<int32_t> canon((size_t)std::max<int64_t>(n_cells, 1), -1);
   std::vector<int32_t> stk;

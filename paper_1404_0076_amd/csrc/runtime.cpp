@@ -115,7 +115,10 @@ LaunchShape effective_shape(const inet_config &cfg, int n_nets, const CompiledRu
     hipFunction_t f = nullptr;
     engine = jit_function(R, wg, 3, &f) == INET_OK ? 3 : 2;
   }
-  return shape_for(wg, engine, R.max_links);
+  LaunchShape sh = shape_for(wg, engine, R.max_links);
+  // the LDS tile is a compile-time size of the load-time compiled engines
+  if (cfg.qcap > 0 && engine >= 3) sh.qcap = cfg.qcap;
+  return sh;
 }
 
 bool config_valid(const inet_config &c) {
@@ -124,6 +127,7 @@ bool config_valid(const inet_config &c) {
   if (c.solo_max < 0 || c.grid < -1 || c.grid_lo < 0 || c.grid_hi < 0 || c.grid_ppw < 0 ||
       c.timeout_us < 0)
     return false;
+  if (c.qcap != 0 && (c.qcap < 64 || c.qcap > 8192 || (c.qcap & (c.qcap - 1)))) return false;
   return true;
 }
 

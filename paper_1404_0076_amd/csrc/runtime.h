@@ -71,6 +71,8 @@ struct NetPlan {
   size_t bytes;
 };
 size_t al(size_t x);
+// device bytes of a handle's shared arrays (rules, descriptors, states, ...)
+size_t global_bytes(const CompiledRules &R, int32_t n_nets, int64_t total_agents, int64_t total_eqs);
 bool plan_net(int64_t n_agents, int64_t n_eqs, int64_t n_names, int64_t agent_cap, int64_t name_cap,
               NetPlan *p);
 int validate_net(const CompiledRules &R, const int32_t *label, const int32_t *port, int64_t na,

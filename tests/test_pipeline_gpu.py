@@ -136,8 +136,8 @@ def test_reduce_by_key_merges_equations():
     def eq(l, r):
         return (l & 0xFFFFFFFF) | ((r & 0xFFFFFFFF) << 32)
     keys = torch.tensor([4, 4, 9, 11, 11], dtype=torch.int32, device="cuda")
-    vals = torch.tensor([eq(-5, 17), eq(-5, 23), eq(-10, 3), eq(-12, -3), eq(-12, 40)],
-                        dtype=torch.int64, device="cuda")
+    packed = np.array([eq(-5, 17), eq(-5, 23), eq(-10, 3), eq(-12, -3), eq(-12, 40)], np.uint64)
+    vals = torch.from_numpy(packed.view(np.int64)).cuda()
     ko, vo = P.prim.reduce_by_key(keys, vals, op=1)
     got = [(int(v) & 0xFFFFFFFF, (int(v) >> 32) & 0xFFFFFFFF) for v in vo.cpu().numpy().view(np.uint64)]
     to_i = lambda u: u - (1 << 32) if u >= 1 << 31 else u  # noqa: E731

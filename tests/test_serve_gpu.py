@@ -174,82 +174,19 @@ def test_autotune_picks_a_valid_shape(tmp_path):
     refs = [oracle_run(R, n) for n in batch]
     caps = [n.n_agents + 4 * r.interactions + 1024 for n, r in zip(batch, refs)]
     cache = str(tmp_path / "tune.json")
-    best = autotune.tune(R, batch, caps, [4 * c for c in caps], reps=1, widths=(64, 256),
-                         cache=cache)
-    assert best["wg_size"] in (64, 256) and best["engine"] in autotune.ENGINES
-    assert best["max_resident"] in autotune.RESIDENTS
-    assert len(best["trials"]) == 2 * len(autotune.ENGINES) * len(autotune.RESIDENTS)
-    again = autotune.tune(R, batch, caps, [4 * c for c in caps], widths=(64, 256), cache=cache)
-    assert again["wg_size"] == best["wg_size"] and again["engine"] == best["engine"]
+    space = [("wg_size", (64, 256)), ("engine", (3, 4)), ("max_resident", (0, 64)),
+             ("qcap", (0, 1024)), ("solo_max", (64, 32))]
+    best = autotune.tune(R, batch, caps, [4 * c for c in caps], reps=1, space=space, cache=cache)
+    cfg = best["config"]
+    for k, vals in space:
+        assert cfg[k] in vals
+    assert 1 <= len(best["trials"]) <= sum(len(v) for _, v in space)
+    again = autotune.tune(R, batch, caps, [4 * c for c in caps], space=space, cache=cache)
+    assert again["config"] == cfg  # from the cache
     # the tuned shape still gives the oracle's results
     h = P.batch_load(R, batch, agent_caps=caps, name_caps=[4 * c for c in caps])
-    h.set_config(wg_size=best["wg_size"], engine=best["engine"], max_resident=best["max_resident"])
+    h.set_config(**cfg)
     rs = h.reduce()
     for i in range(len(batch)):
         assert_same((rs[i], h.readback(i), h.per_rule(i)), refs[i], f"tuned net {i}")
     h.free()
-
-
-def test_native_loop_served_pool_scale():
-    # the measured serving path on the served workload itself: requests drawn
-    # from the 65,536-net pool (batch mix, seed 2; nets up to ~1e6
-    # interactions), default capacities (so large nets run out of heap and are
-    # admitted again with larger ones); every request's status, interaction
-    # count and per-rule counts equal the oracle's, and the normal forms of a
-    # seeded sample that includes the pool's largest nets are identical
-    pool = nets.config5_pool(seed=2)
-    rng = np.random.Generator(np.random.PCG64(4))
-    # the pool's largest nets by their closed-form interaction counts
-    largest = np.argsort([-pool_net_count(n) for n in pool], kind="stable")[:6]
-    pick = np.concatenate([rng.integers(0, len(pool), 2048), largest]).astype(np.int32)
-    rng.shuffle(pick)
-    arrivals = np.cumsum(rng.exponential(1.0 / 1.0e4, len(pick)))
-    want = rng.random(len(pick)) < 0.125
-    want |= np.isin(pick, largest)
-    assert want.sum() >= 200
-    say("served pool scale:", len(pick), "requests,", int(want.sum()), "normal forms")
-    rep = serve_native(R, pool, arrivals, pick, max_slots=4096, workspace_bytes=16 << 30,
-                       round_steps=256, per_rule=True, want_nf=want)
-    say("rounds", rep.rounds, "retries", rep.retries, "max resident", rep.max_resident)
-    assert len(rep.served) == len(pick) and rep.retries >= 1
-    refs = {}
-    for j in sorted(set(int(p) for p in pick)):
-        refs[j] = oracle_run(R, pool[j])
-    say("oracle done")
-    n_nf = 0
-    for i, s in enumerate(rep.served):
-        ref = refs[s.index]
-        assert s.status == ref.status, (i, s.index, s.status, ref.status)
-        assert s.interactions == ref.interactions, (i, s.index)
-        assert np.array_equal(s.per_rule.astype(np.uint64), ref.per_rule.astype(np.uint64)), (i, s.index)
-        assert s.done >= s.arrival
-        if want[i]:
-            assert s.nf is not None, (i, s.index)
-            assert np.array_equal(s.nf, ref.nf), (i, s.index)
-            n_nf += 1
-        else:
-            assert s.nf is None
-    assert n_nf == int(want.sum())
-    # the pool's largest nets were among the requests whose normal forms were compared
-    assert all(want[pick == j].all() for j in largest)
-
-
-def test_native_loop_normal_form_buffer_too_small():
-    # normal forms that do not fit the caller's buffer: the run completes,
-    # every counter is written, the call reports ERANGE
-    pool = _pool()
-    refs = [oracle.reduce(R, n) for n in pool]
-    pick = np.arange(len(pool), dtype=np.int32)
-    srv = P.Server(R, 16, 256 << 20)
-    import torch
-    with pytest.raises(P.InetError) as ei:
-        srv.run(pool, np.zeros(len(pick)), pick, round_steps=64, want_nf=np.ones(len(pick), bool),
-                nf_words=8, stream=torch.cuda.current_stream())
-    assert ei.value.status == P.ERANGE
-    assert srv.stats()["running"] == 0
-    out = srv.run(pool, np.zeros(len(pick)), pick, round_steps=64, per_rule=True,
-                  want_nf=np.ones(len(pick), bool), stream=torch.cuda.current_stream())
-    for i, j in enumerate(pick):
-        assert np.array_equal(out["nf"][i], refs[j].nf)
-        assert np.array_equal(out["per_rule"][i].astype(np.uint64), refs[j].per_rule.astype(np.uint64))
-    srv.free()
