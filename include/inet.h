@@ -313,6 +313,30 @@ int inet_prim_reduce_by_key(const uint32_t *d_keys, const uint64_t *d_vals, int6
                             uint32_t *d_keys_out, uint64_t *d_vals_out, int32_t op,
                             int64_t *n_out, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): load,
+ * reduce and read back one net like inet_load + inet_reduce + inet_readback,
+ * but with every device array the kernels need (rule table, descriptor,
+ * state, agent heap, name cells, queues, residuals, initial image, counters)
+ * carved out of a static device array of INET_NOALLOC_SCRATCH_BYTES that
+ * the library holds on each device until the process ends; no hipMalloc,
+ * hipFree or run-time compilation happens (the ahead-of-time engine 2 runs,
+ * 1024 lanes, one workgroup, then the pointer-jumping pass).  Inputs are the
+ * host arrays of inet_load (copied on `stream`), capacities as there; a net
+ * whose workspace (inet_workspace_bytes) exceeds the array gives INET_ENOMEM
+ * before anything runs.  max_steps as for inet_reduce.  Outputs: *out, and
+ * when nf_len is not NULL the canonical normal-form stream into nf (nf_cap
+ * int32 words; INET_ERANGE with *nf_len set if it does not fit).  Returns
+ * the net's status.  The call synchronises `stream`.  Every call on a device
+ * shares that device's array and overwrites what the previous call left;
+ * calls that overlap on one device race (serialise them). */
+#define INET_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int inet_reduce_noalloc(const inet_rules *rules, const int32_t *label, const int32_t *port,
+                        int32_t n_agents, const int32_t *eq_lhs, const int32_t *eq_rhs,
+                        int32_t n_eqs, int32_t n_names, int64_t agent_cap, int64_t name_cap,
+                        uint64_t max_steps, hipStream_t stream, inet_result *out, int32_t *nf,
+                        int64_t nf_cap, int64_t *nf_len);
+
 /* ------------------------------------------------------------------------
  * Continuous batching (serving).  A server owns one caller-provided device
  * buffer and up to max_slots resident nets.  inet_server_submit admits a net

@@ -32,6 +32,7 @@ EXPORTS = [
     "inet_server_per_rule", "inet_server_release", "inet_server_stats", "inet_server_free",
     "inet_jit_build", "inet_server_run", "inet_reduce_pipeline", "inet_cells",
     "inet_prim_scan", "inet_prim_select", "inet_prim_sort_pairs", "inet_prim_reduce_by_key",
+    "inet_reduce_noalloc",
 ]
 
 
@@ -101,6 +102,8 @@ def library():
             "inet_prim_scan": [_P, _P, _I64, _P], "inet_prim_select": [_P, _P, _I64, _U64, _P, _P],
             "inet_prim_sort_pairs": [_P, _P, _I64, _P],
             "inet_prim_reduce_by_key": [_P, _P, _I64, _P, _P, _I32, _P, _P],
+            "inet_reduce_noalloc": [_P, _P, _P, _I32, _P, _P, _I32, _I32, _I64, _I64, _U64, _P, _P,
+                                    _P, _I64, _P],
             "inet_rule_bytes": [_P, _P, _I32], "inet_num_nets": [_P],
             "inet_rules_check": [_P, _P, _P, _P, _P, _I32],
             "inet_jit_build": [_P, ctypes.c_char_p, _P, _P, ctypes.c_size_t],
@@ -402,6 +405,31 @@ def reduce_net(rules, net, agent_cap: int = 0, name_cap: int = 0, wg_size: int =
         h.free()
         return res, nf, pr
     raise InetError(ENOMEM, "reduce_net")
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # INET_NOALLOC_SCRATCH_BYTES
+
+
+def reduce_noalloc(rules, net, agent_cap: int = 0, name_cap: int = 0, max_steps: int = 0,
+                   nf_words: int = 1 << 22, stream=None):
+    """inet_reduce_noalloc: one net loaded, reduced and read back inside the
+    library's static device array (no device allocation).  Returns (Result,
+    normal-form stream or None, status)."""
+    s, _ = _stream_handle(stream)
+    R = RulesArg(rules)
+    la, po = _arr(net.label, np.int32), _arr(net.port, np.int32)
+    el, er = _arr(net.eq_lhs, np.int32), _arr(net.eq_rhs, np.int32)
+    r = _Result()
+    buf = np.zeros(max(1, nf_words), np.int32)
+    n = ctypes.c_int64(0)
+    rc = library().inet_reduce_noalloc(R.ptr, la.ctypes.data, po.ctypes.data, net.n_agents,
+                                       el.ctypes.data, er.ctypes.data, net.n_eqs, net.n_names,
+                                       agent_cap, name_cap, max_steps, s, ctypes.byref(r),
+                                       buf.ctypes.data, buf.size, ctypes.byref(n))
+    if rc not in (OK, STUCK, ELIMIT):
+        raise InetError(rc, "inet_reduce_noalloc")
+    res = _result(r)
+    return res, (buf[: n.value].copy() if res.status in (OK, STUCK) else None), rc
 
 
 def _result(r) -> Result:
