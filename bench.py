@@ -511,6 +511,8 @@ def main():
         alg += float(np.dot(h.per_rule(i).astype(np.float64), rb))
     kmean = float(kern_ms.mean())
     wkey = f"{args.workload}/{args.n_nets}/{args.seed}/wg{wg}/engine{h.get_config()['engine']}"
+    if any(extra.values()):
+        wkey += "/" + ",".join(f"{k}{v}" for k, v in sorted(extra.items()) if v)
     achieved = alg / (kmean * 1e-3) / 1e9
     out = {
         "metric": METRIC, "value": value, "unit": "interactions/s", "n_gpus": 1,

@@ -141,7 +141,9 @@ typedef struct {
                                step together, at every frontier width)    */
   int32_t solo_max;         /* engine 3, wider engines: wave 0 steps alone
                                while at most this many pairs are active
-                               (0: 64)                                     */
+                               (1..4096, 0: 64; a compile-time bound of the
+                               load-time compiled engine, one code object
+                               per value)                                  */
   int32_t grid;             /* a handle holding one net, engine 3: 0 the
                                multi-workgroup engine over every workgroup
                                that can be resident; > 0 over at most this
@@ -233,6 +235,15 @@ int inet_readback(inet_net *h, int32_t net, int32_t *buf, int64_t cap, int64_t *
 
 /* Per-rule interaction counts of net i (cap >= n_rules words). */
 int inet_per_rule(inet_net *h, int32_t net, uint64_t *counts, int32_t cap);
+
+/* Opt-in diagnostic of the available parallelism (the active pairs per loop
+ * iteration that Section 4.1 discusses): from the next reduction on, net
+ * `net` writes the number of active pairs it reduces in parallel step s to
+ * d_buf[s] (caller-owned device memory of cap int32, written on the device)
+ * for every step s < cap; cap 0 turns it off.  A resumed reduction continues
+ * at its step count.  The sum over a finished net's steps is its interaction
+ * count plus its residual pairs. */
+int inet_set_trace(inet_net *h, int32_t net, int32_t *d_buf, int64_t cap);
 
 /* The raw name cells of a finished net (a diagnostic of the pointer-jumping
  * pass): cell x (0 <= x < names_used) holds EMPTY (0x7fffffff) while no

@@ -30,7 +30,7 @@ EXPORTS = [
     "inet_graph_launch", "inet_server_create", "inet_server_set_config", "inet_server_net_bytes",
     "inet_server_submit", "inet_server_step", "inet_server_poll", "inet_server_result",
     "inet_server_per_rule", "inet_server_release", "inet_server_stats", "inet_server_free",
-    "inet_jit_build", "inet_server_run", "inet_reduce_pipeline", "inet_cells",
+    "inet_jit_build", "inet_server_run", "inet_reduce_pipeline", "inet_cells", "inet_set_trace",
     "inet_prim_scan", "inet_prim_select", "inet_prim_sort_pairs", "inet_prim_reduce_by_key",
     "inet_reduce_noalloc",
 ]
@@ -98,7 +98,7 @@ def library():
             "inet_reduce_async": [_P, _P, _U64], "inet_results": [_P, _P, _P],
             "inet_reduce": [_P, _P, _U64, _P], "inet_reset": [_P, _P],
             "inet_readback": [_P, _I32, _P, _I64, _P], "inet_per_rule": [_P, _I32, _P, _I32],
-            "inet_cells": [_P, _I32, _P, _I64, _P],
+            "inet_cells": [_P, _I32, _P, _I64, _P], "inet_set_trace": [_P, _I32, _P, _I64],
             "inet_prim_scan": [_P, _P, _I64, _P], "inet_prim_select": [_P, _P, _I64, _U64, _P, _P],
             "inet_prim_sort_pairs": [_P, _P, _I64, _P],
             "inet_prim_reduce_by_key": [_P, _P, _I64, _P, _P, _I32, _P, _P],
@@ -251,6 +251,19 @@ class Handle:
         out.update({k: getattr(cfg, k) for k in CONFIG_KEYS})
         return out
 
+    def set_trace(self, net: int = 0, buf=None):
+        """Record the active pairs of each parallel step of ``net`` into the
+        int32 device tensor ``buf`` (inet_set_trace); None turns it off."""
+        import torch
+        if buf is None:
+            self._check(library().inet_set_trace(self._h, net, None, 0), "inet_set_trace")
+            self._trace = None
+            return
+        assert buf.is_cuda and buf.dtype == torch.int32 and buf.is_contiguous()
+        self._trace = buf
+        self._check(library().inet_set_trace(self._h, net, ctypes.c_void_p(buf.data_ptr()),
+                                             buf.numel()), "inet_set_trace")
+
     def cells(self, net: int = 0) -> np.ndarray:
         """The raw name cells of a finished net (inet_cells), after results()."""
         n = ctypes.c_int64(0)
@@ -382,6 +395,26 @@ def load(rules, net: "nets.Net", agent_cap: int = 0, name_cap: int = 0, stream=N
     if rc:
         raise InetError(rc, "inet_load")
     return Handle(h, ws, rules, 1)
+
+
+def parallelism(rules, net, agent_cap: int = 0, name_cap: int = 0, max_steps: int = 1 << 22,
+                **config) -> np.ndarray:
+    """Active pairs reduced in each parallel step of ``net`` (the available
+    parallelism of Section 4.1), from a reduction with inet_set_trace."""
+    import torch
+    agent_cap = agent_cap or max(4 * net.n_agents + 4096, 1 << 16)
+    name_cap = name_cap or 4 * agent_cap
+    h = load(rules, net, agent_cap=agent_cap, name_cap=name_cap)
+    h.set_config(**config)
+    buf = torch.zeros(max_steps, dtype=torch.int32, device="cuda")
+    h.set_trace(0, buf)
+    res = h.reduce()[0]
+    if res.status not in (OK, STUCK):
+        h.free()
+        raise InetError(res.status, "parallelism")
+    out = buf[: min(int(res.steps), max_steps)].cpu().numpy().copy()
+    h.free()
+    return out
 
 
 def reduce_net(rules, net, agent_cap: int = 0, name_cap: int = 0, wg_size: int = 0,

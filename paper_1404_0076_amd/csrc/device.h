@@ -1070,12 +1070,18 @@ struct RuleView {
 
 // One net on one workgroup, from its saved state: the initial equations are
 // linked (first launch), then parallel steps run until no active pair is
-// left, the absolute step budget `stop` is reached, an error occurs, or more
-// than `hi` pairs are active (a multi-workgroup engine then takes the net
-// over); the state is saved back into the net's NetState and queues.  With
-// `hb`, the step count is published there every 1024 steps (progress seen by
-// workgroups waiting on this one).
-template <int WG, int QCAP, int ENGINE, int MAXL>
+// left, the absolute step budget `stop` is reached or an error occurs; the
+// state is saved back into the net's NetState and queues.  NARROW: the
+// narrow phase of the multi-workgroup engine, which also stops once more than
+// `hi` pairs are active (the other workgroups then take the net over) and
+// publishes its step count in *hb every 1024 steps (progress seen by the
+// workgroups waiting on it).  TRACE: the number of active pairs of each step
+// goes to the net's trace buffer, if it has one.  Both are compile-time so
+// that the batch kernel carries neither.  SOLO_MAX: wider engines step with
+// wave 0 alone while at most this many pairs are active (a compile-time
+// bound: the one-wave loop is then specialised for it).
+template <int WG, int QCAP, int ENGINE, int MAXL, bool NARROW = false, bool TRACE = false,
+          int SOLO_MAX = 64>
 __device__ __forceinline__ void engine_net(EngineLds<QCAP> &S, const NetDesc &D, const RuleView &RV,
                                            unsigned stop, int flags, int hi, const KParams &kp,
                                            int *hb) {
@@ -1177,7 +1183,10 @@ __device__ __forceinline__ void engine_net(EngineLds<QCAP> &S, const NetDesc &D,
         const int tot = n + nh;
         if (!(tot > 0 && tot <= limit && C.err >= 0 && steps < stop)) break;
         if (tot > maxf) maxf = tot;
-        if (hb && (steps & 1023u) == 0 && __lane_id() == 0) gstore(hb, (int)steps);
+        if constexpr (NARROW)
+          if ((steps & 1023u) == 0 && __lane_id() == 0) gstore(hb, (int)steps);
+        if constexpr (TRACE)
+          if (D.trace && steps < (unsigned)D.trace_cap && __lane_id() == 0) D.trace[steps] = tot;
         const Pair *cq_l = S.q[cur];
         const gint2 *cq_g = cur ? queue1 : queue0;
         Pair *nq_l = S.q[cur ^ 1];
@@ -1234,10 +1243,13 @@ __device__ __forceinline__ void engine_net(EngineLds<QCAP> &S, const NetDesc &D,
         if (C.err < 0) S.status = C.err;
       }
     };
-    const int solo_max = kp.solo_max < hi ? kp.solo_max : hi;
+    // the one-wave loop specialised for a compile-time bound; a hand-over
+    // threshold below it (narrow phase) takes a second, generic copy
+    const int solo_max = (NARROW && hi < SOLO_MAX) ? hi : SOLO_MAX;
     if constexpr (WG == 64 && !LANE) {
       __syncthreads();
-      solo(hi);
+      if (!NARROW) solo(0x7fffffff);
+      else solo(hi);
       if (rc_lane) atomicAdd(&S.rc[tid], (unsigned long long)rc_lane);
       if (loops_lane) atomicAdd(&S.loops, loops_lane);
       __syncthreads();
@@ -1252,9 +1264,12 @@ __device__ __forceinline__ void engine_net(EngineLds<QCAP> &S, const NetDesc &D,
       for (;;) {
         __syncthreads();
         const int n = S.cnt[ci];
-        if (n == 0 || S.status < 0 || steps >= stop || n > hi) break;
+        if (n == 0 || S.status < 0 || steps >= stop || (NARROW && n > hi)) break;
         if (!LANE && n <= solo_max) {
-          if (tid < 64) solo(solo_max);
+          if (tid < 64) {
+            if (!NARROW || hi >= SOLO_MAX) solo(SOLO_MAX);
+            else solo(hi);
+          }
           __syncthreads();
           steps = S.steps;
           cur = S.cur;
@@ -1265,7 +1280,10 @@ __device__ __forceinline__ void engine_net(EngineLds<QCAP> &S, const NetDesc &D,
         if (tid == 0) {
           S.cnt[cnn] = 0;
           if (n > S.maxf) S.maxf = n;
-          if (hb && (steps & 1023u) == 0) gstore(hb, (int)steps);
+          if constexpr (NARROW)
+            if ((steps & 1023u) == 0) gstore(hb, (int)steps);
+          if constexpr (TRACE)
+            if (D.trace && steps < (unsigned)D.trace_cap) D.trace[steps] = n;
         }
         const Pair *cq_l = S.q[cur];
         const gint2 *cq_g = cur ? queue1 : queue0;
@@ -1295,12 +1313,14 @@ __device__ __forceinline__ void engine_net(EngineLds<QCAP> &S, const NetDesc &D,
   for (;;) {
     __syncthreads();
     const int n = S.cnt[ci];
-    if (n == 0 || S.status < 0 || steps >= stop || n > hi) break;
+    if (n == 0 || S.status < 0 || steps >= stop || (NARROW && n > hi)) break;
     const int cn = ci == 2 ? 0 : ci + 1;
     const int cnn = cn == 2 ? 0 : cn + 1;
     if (tid == 0) {
       S.cnt[cnn] = 0;
       if (n > S.maxf) S.maxf = n;
+      if constexpr (TRACE)
+        if (D.trace && steps < (unsigned)D.trace_cap) D.trace[steps] = n;
     }
     const Pair *cq_l = S.q[cur];
     const gint2 *cq_g = cur ? queue1 : queue0;
@@ -1401,7 +1421,7 @@ __device__ __forceinline__ RuleView load_rules(const int *__restrict__ g_rules, 
 
 // the persistent batch kernel: each workgroup takes nets from a device
 // counter in the given order and runs each to normal form (or the budget)
-template <int WG, int QCAP, int ENGINE, int MAXL>
+template <int WG, int QCAP, int ENGINE, int MAXL, bool TRACE = false, int SOLO_MAX = 64>
 __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
                                             const int *__restrict__ order, int n_nets,
                                             int *counter, const int *__restrict__ g_rules,
@@ -1420,7 +1440,8 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
     const unsigned steps0 = D.st->steps;
     // per-launch step budget (saturating)
     const unsigned stop = (max_steps > 0xffffffffu - steps0) ? 0xffffffffu : steps0 + max_steps;
-    engine_net<WG, QCAP, ENGINE, MAXL>(S, D, RV, stop, flags, 0x7fffffff, kp, nullptr);
+    engine_net<WG, QCAP, ENGINE, MAXL, false, TRACE, SOLO_MAX>(S, D, RV, stop, flags, 0x7fffffff,
+                                                              kp, nullptr);
   }
 }
 
@@ -1454,7 +1475,7 @@ __device__ __forceinline__ int logical_wg(int b, int G) {
   return before + (b >> 3);
 }
 
-template <int WG, int QCAP, int MAXL>
+template <int WG, int QCAP, int MAXL, bool TRACE = false, int SOLO_MAX = 64>
 __device__ __forceinline__ void grid_body(const NetDesc *__restrict__ descs,
                                           const int *__restrict__ g_rules, int ns, int nr,
                                           unsigned max_steps, int flags, const KParams &kp) {
@@ -1483,7 +1504,8 @@ __device__ __forceinline__ void grid_body(const NetDesc *__restrict__ descs,
     const unsigned steps0 = st->steps;
     stop = (max_steps > 0xffffffffu - steps0) ? 0xffffffffu : steps0 + max_steps;
     if (tid == 0) ctl->stop = stop;
-    engine_net<WG, QCAP, 3, MAXL>(S, D, RV, stop, 0, hi, kp, &ctl->heartbeat);
+    engine_net<WG, QCAP, 3, MAXL, true, TRACE, SOLO_MAX>(S, D, RV, stop, 0, hi, kp,
+                                                         &ctl->heartbeat);
   }
   for (;;) {
     // ---- barrier between epochs
@@ -1505,6 +1527,8 @@ __device__ __forceinline__ void grid_body(const NetDesc *__restrict__ descs,
             steps = ctl->steps + 1;
             const int done_n = ctl->n;
             if (done_n > st->max_frontier) st->max_frontier = done_n;
+            if constexpr (TRACE)
+              if (D.trace && ctl->steps < (unsigned)D.trace_cap) D.trace[ctl->steps] = done_n;
           } else {
             n = st->frontier;
             cur = st->parity;
@@ -1579,7 +1603,9 @@ __device__ __forceinline__ void grid_body(const NetDesc *__restrict__ descs,
     seen = S.bcast[4];
     if (mode == GM_NARROW) {
       part = me == 0;
-      if (part) engine_net<WG, QCAP, 3, MAXL>(S, D, RV, stop, 0, hi, kp, &ctl->heartbeat);
+      if (part)
+        engine_net<WG, QCAP, 3, MAXL, true, TRACE, SOLO_MAX>(S, D, RV, stop, 0, hi, kp,
+                                                             &ctl->heartbeat);
       continue;
     }
     // ---- one parallel step shared by the first g workgroups
@@ -1644,8 +1670,9 @@ __global__ __launch_bounds__(WG) void k_reduce(const NetDesc *__restrict__ descs
                                                int *counter, const int *__restrict__ g_rules,
                                                int ns, int nr, unsigned max_steps, int flags,
                                                KParams kp) {
-  reduce_body<WG, QCAP, ENGINE, MAXL>(descs, order, n_nets, counter, g_rules, ns, nr, max_steps,
-                                      flags, kp);
+  // the ahead-of-time engines always carry the trace (they are not the fast path)
+  reduce_body<WG, QCAP, ENGINE, MAXL, true>(descs, order, n_nets, counter, g_rules, ns, nr,
+                                            max_steps, flags, kp);
 }
 
 // pointer jumping over one net's cells with the whole grid (single big nets):

@@ -91,6 +91,11 @@ struct NetDesc {
   int32_t n_eqs0;
   int32_t n_names0;
   int32_t order;  // position in the launch order (largest nets first)
+  // opt-in diagnostic: active pairs reduced in each parallel step (trace[s]
+  // for steps s < trace_cap), or null
+  int32_t *trace;
+  int32_t trace_cap;
+  int32_t pad_;
 };
 
 // a net admitted by the serving loop: its descriptor and the slot it takes
@@ -134,7 +139,6 @@ struct GridCtl {
 // tunables of the reduction kernel (by value)
 struct KParams {
   GridCtl *ctl;         // multi-workgroup engine: its control block (else null)
-  int32_t solo_max;     // one-wave steps while at most this many pairs are active
   int32_t grid_lo;      // multi-workgroup steps while more than this many are active
   int32_t grid_hi;      // workgroup 0 hands over once more than this many are active
   int32_t grid_ppw;     // target active pairs per workgroup in a multi-workgroup step

@@ -41,7 +41,7 @@ struct Module {
 std::mutex g_mu;
 std::map<std::string, Module> g_mods;
 
-std::string source_for(const CompiledRules &R, int engine, int wg, int qcap) {
+std::string source_for(const CompiledRules &R, int engine, int wg, int qcap, int trace, int solo) {
   std::ostringstream o;
   o << "#define INET_STATIC_RULES 1\n#include \"inet_internal.h\"\n";
   o << "namespace inet { namespace rt {\n";
@@ -67,13 +67,14 @@ std::string source_for(const CompiledRules &R, int engine, int wg, int qcap) {
       << "(const inet::NetDesc *__restrict__ d, const int *__restrict__ ord, int n, int *ctr,"
          " const int *__restrict__ r, int ns, int nr, unsigned ms, int flags, inet::KParams kp) {\n"
       << "  inet::reduce_body<" << wg << ", " << sh.qcap << ", " << engine << ", " << maxl
+      << ", " << (trace ? "true" : "false") << ", " << solo
       << ">(d, ord, n, ctr, r, ns, nr, ms, flags, kp);\n}\n";
     if (engine == 3)
       o << "extern \"C\" __global__ __launch_bounds__(" << wg << ") void inet_grid_" << wg
         << "(const inet::NetDesc *__restrict__ d, const int *__restrict__ r, int ns, int nr,"
            " unsigned ms, int flags, inet::KParams kp) {\n"
-        << "  inet::grid_body<" << wg << ", " << sh.qcap << ", " << maxl
-        << ">(d, r, ns, nr, ms, flags, kp);\n}\n";
+        << "  inet::grid_body<" << wg << ", " << sh.qcap << ", " << maxl << ", "
+        << (trace ? "true" : "false") << ", " << solo << ">(d, r, ns, nr, ms, flags, kp);\n}\n";
   }
   return o.str();
 }
@@ -94,8 +95,8 @@ std::string key_for(const CompiledRules &R, const std::string &arch) {
 
 // compile the specialised engine; code object into *code (no device needed)
 int compile_code(const CompiledRules &R, const std::string &arch, int engine, int wg, int qcap,
-                 std::vector<char> *code, std::string *log_out) {
-  const std::string src = source_for(R, engine, wg, qcap);
+                 int trace, int solo, std::vector<char> *code, std::string *log_out) {
+  const std::string src = source_for(R, engine, wg, qcap, trace, solo);
   if (const char *dump = std::getenv("INET_JIT_DUMP")) {  // inspection aid
     if (FILE *f = std::fopen(dump, "w")) {
       std::fputs(src.c_str(), f);
@@ -133,9 +134,9 @@ int compile_code(const CompiledRules &R, const std::string &arch, int engine, in
 }
 
 int build_module(const CompiledRules &R, const std::string &arch, int engine, int wg, int qcap,
-                 Module *M) {
+                 int trace, int solo, Module *M) {
   std::vector<char> code;
-  int rc = compile_code(R, arch, engine, wg, qcap, &code, &M->log);
+  int rc = compile_code(R, arch, engine, wg, qcap, trace, solo, &code, &M->log);
   if (rc) return rc;
   if (hipModuleLoadData(&M->mod, code.data()) != hipSuccess) return INET_EHIP;
   const std::string name = "inet_static_" + std::to_string(wg);
@@ -151,11 +152,11 @@ int build_module(const CompiledRules &R, const std::string &arch, int engine, in
 
 // Kernel of engine 3 or 4 for the rule table and engine width (built on first
 // use); with `grid`, the multi-workgroup engine of one net (engine 3 only).
-static int jit_kernel(const CompiledRules &R, int wg, int qcap, int engine, bool grid,
-                      hipFunction_t *out) {
+static int jit_kernel(const CompiledRules &R, int wg, int qcap, int engine, bool grid, int trace,
+                      int solo, hipFunction_t *out) {
   if (engine != 3 && engine != 4) return INET_EINVAL;
   if (!shape_supported(wg) || (grid && engine != 3)) return INET_EINVAL;
-  if (qcap < 64 || qcap > 8192 || (qcap & (qcap - 1))) return INET_EINVAL;
+  if (qcap < 64 || qcap > 8192 || (qcap & (qcap - 1)) || solo < 1 || solo > 4096) return INET_EINVAL;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return INET_EHIP;
   hipDeviceProp_t prop;
@@ -163,12 +164,13 @@ static int jit_kernel(const CompiledRules &R, int wg, int qcap, int engine, bool
   std::string arch(prop.gcnArchName);
   const std::string key = key_for(R, arch) + "/" + std::to_string(dev) + "/" +
                           std::to_string(engine) + "/" + std::to_string(wg) + "/" +
-                          std::to_string(qcap);
+                          std::to_string(qcap) + "/" + std::to_string(solo) +
+                          (trace ? "/trace" : "");
   std::lock_guard<std::mutex> lock(g_mu);
   Module &M = g_mods[key];
   if (M.failed) return INET_ENOSYS;
   if (!M.mod) {
-    int rc = build_module(R, arch, engine, wg, qcap, &M);
+    int rc = build_module(R, arch, engine, wg, qcap, trace, solo, &M);
     if (rc) {
       M.failed = true;
       if (std::getenv("INET_JIT_LOG")) std::fprintf(stderr, "inet jit: %d\n%s\n", rc, M.log.c_str());
@@ -180,14 +182,15 @@ static int jit_kernel(const CompiledRules &R, int wg, int qcap, int engine, bool
 }
 
 int jit_function(const CompiledRules &R, int wg, int engine, hipFunction_t *out) {
-  return jit_kernel(R, wg, shape_for(wg, engine, R.max_links).qcap, engine, false, out);
+  const LaunchShape sh = shape_for(wg, engine, R.max_links);
+  return jit_kernel(R, wg, sh.qcap, engine, false, 0, sh.solo, out);
 }
 
 int jit_launch(const CompiledRules &R, const LaunchShape &sh, int grid, const NetDesc *d,
                const int32_t *ord, int n, int32_t *ctr, const int32_t *r, uint32_t ms, int flags,
                const KParams &kp, hipStream_t s) {
   hipFunction_t f = nullptr;
-  int rc = jit_kernel(R, sh.wg, sh.qcap, sh.engine, false, &f);
+  int rc = jit_kernel(R, sh.wg, sh.qcap, sh.engine, false, sh.trace, sh.solo, &f);
   if (rc) return rc;
   int ns = R.ns, nr = R.nr;
   KParams k = kp;
@@ -203,7 +206,7 @@ int jit_grid_launch(const CompiledRules &R, const LaunchShape &sh, int grid, con
                     const int32_t *r, uint32_t ms, int flags, const KParams &kp, hipStream_t s) {
   if (sh.engine != 3 || !kp.ctl) return INET_EINVAL;
   hipFunction_t f = nullptr;
-  int rc = jit_kernel(R, sh.wg, sh.qcap, 3, true, &f);
+  int rc = jit_kernel(R, sh.wg, sh.qcap, 3, true, sh.trace, sh.solo, &f);
   if (rc) return rc;
   int ns = R.ns, nr = R.nr;
   KParams k = kp;
@@ -217,7 +220,7 @@ int jit_grid_launch(const CompiledRules &R, const LaunchShape &sh, int grid, con
 
 static int occupancy_of(const CompiledRules &R, const LaunchShape &sh, bool grid, int *per_cu) {
   hipFunction_t f = nullptr;
-  int rc = jit_kernel(R, sh.wg, sh.qcap, sh.engine, grid, &f);
+  int rc = jit_kernel(R, sh.wg, sh.qcap, sh.engine, grid, sh.trace, sh.solo, &f);
   if (rc) return rc;
   const size_t dyn = (size_t)(R.ns * R.ns + R.nr * RT_WORDS + R.ns) * 4;
   return hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, f, sh.wg, dyn) == hipSuccess
@@ -249,7 +252,7 @@ extern "C" int inet_jit_build(const inet_rules *rules, const char *arch, size_t 
   for (int engine = 3; engine <= 4 && rc == INET_OK; engine++) {
     std::vector<char> code;
     rc = inet::compile_code(R, arch, engine, 1024, inet::shape_for(1024, engine, R.max_links).qcap,
-                            &code, &msg);
+                            0, 64, &code, &msg);
     total += code.size();
   }
   if (log && log_cap) {

@@ -118,6 +118,7 @@ LaunchShape effective_shape(const inet_config &cfg, int n_nets, const CompiledRu
   LaunchShape sh = shape_for(wg, engine, R.max_links);
   // the LDS tile is a compile-time size of the load-time compiled engines
   if (cfg.qcap > 0 && engine >= 3) sh.qcap = cfg.qcap;
+  if (cfg.solo_max > 0 && engine >= 3) sh.solo = cfg.solo_max;
   return sh;
 }
 
@@ -128,6 +129,7 @@ bool config_valid(const inet_config &c) {
       c.timeout_us < 0)
     return false;
   if (c.qcap != 0 && (c.qcap < 64 || c.qcap > 8192 || (c.qcap & (c.qcap - 1)))) return false;
+  if (c.solo_max > 4096) return false;
   return true;
 }
 
@@ -143,7 +145,6 @@ int kparams_for(const inet_config &c, GridCtl *ctl, KParams *kp) {
   }
   *kp = KParams{};
   kp->ctl = ctl;
-  kp->solo_max = c.solo_max > 0 ? c.solo_max : 64;
   kp->grid_lo = c.grid_lo > 0 ? c.grid_lo : 1024;
   kp->grid_hi = std::max(c.grid_hi > 0 ? c.grid_hi : 2048, kp->grid_lo);
   kp->grid_ppw = c.grid_ppw;
@@ -168,7 +169,11 @@ int resident_grid(const LaunchShape &sh, const CompiledRules &R, const inet_conf
 }  // namespace inet
 
 namespace {
-LaunchShape shape_of(const inet_net *h) { return inet::effective_shape(h->cfg, h->n_nets, h->rules); }
+LaunchShape shape_of(const inet_net *h) {
+  LaunchShape sh = inet::effective_shape(h->cfg, h->n_nets, h->rules);
+  sh.trace = h->tracing ? 1 : 0;
+  return sh;
+}
 }  // namespace
 
 extern "C" {
@@ -530,6 +535,18 @@ int inet_per_rule(inet_net *h, int32_t net, uint64_t *counts, int32_t cap) {
   if (h->rules.nr == 0) return INET_OK;
   HIPCHK(hipMemcpy(counts, h->d_per_rule + (size_t)net * h->rules.nr, 8 * (size_t)h->rules.nr,
                    hipMemcpyDeviceToHost));
+  return INET_OK;
+}
+
+int inet_set_trace(inet_net *h, int32_t net, int32_t *d_buf, int64_t cap) {
+  if (!h || net < 0 || net >= h->n_nets || cap < 0 || (cap > 0 && !d_buf)) return INET_EINVAL;
+  NetDesc &D = h->descs[net];
+  D.trace = cap > 0 ? d_buf : nullptr;
+  D.trace_cap = (int32_t)std::min<int64_t>(cap, INT32_MAX);
+  HIPCHK(hipMemcpy(h->d_descs + net, &D, sizeof(NetDesc), hipMemcpyHostToDevice));
+  h->tracing = false;
+  for (const NetDesc &d : h->descs)
+    if (d.trace) h->tracing = true;
   return INET_OK;
 }
 

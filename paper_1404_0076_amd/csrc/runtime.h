@@ -33,6 +33,8 @@ struct LaunchShape {
                // 3: rule-uniform with the rule table compiled in (load time),
                // 4: engine 3 with per-lane atomic reservations (atomic append)
   int maxl;    // largest number of link equations of any rule
+  int trace = 0;  // engines 3 and 4: the kernel variant that records per-step pair counts
+  int solo = 64;  // engine 3: one-wave steps while at most this many pairs are active
 };
 int launch_reset(const NetDesc *d_descs, const int32_t *d_idx, int n, int nr, hipStream_t s);
 int launch_admit(const AdmitRec *d_recs, int n, NetDesc *d_descs, int nr, hipStream_t s);
@@ -123,6 +125,7 @@ struct inet_net {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   bool timed = false;
+  bool tracing = false;                   // some net has a per-step trace buffer
   inet::NetState *h_states = nullptr;     // pinned staging
 };
 

@@ -275,3 +275,38 @@ def test_grid_ackermann_3_7():
     for cfg in ({}, FORCED):
         say("grid ackermann 3 7", cfg)
         assert_same(gpu(rules, net, **cfg), oracle_run(rules, net), f"A(3,7) {cfg}")
+
+
+# ---------------------------------------------------------------------------
+# the available-parallelism trace (active pairs per parallel step)
+
+
+@pytest.mark.parametrize("cfg", [{}, ONE_WG, FORCED, dict(engine=2), dict(wg_size=64)],
+                         ids=["grid", "one", "forced", "engine2", "wave"])
+def test_parallelism_trace(cfg):
+    for rules, net in ((R, nets.mul_net(40, 31)), (R, nets.fib_net(12)),
+                       (nets.algae_rules(), nets.algae_net(14)),
+                       (R, nets.parse_net(nets.ARITH_SIG, "<r, q | S(r) = Z, Add(q, y) = Fib(y)>"))):
+        ref = oracle_run(rules, net)
+        rounds = oracle.reduce(rules, net, schedule="rounds").rounds
+        say("trace", cfg, net.meta.get("family"))
+        tr = P.parallelism(rules, net, **cfg)
+        res = gpu(rules, net, **cfg)[0]
+        # one entry per parallel step (maximal rounds when no pair is left
+        # without a rule: the oracle's rounds count reductions only), every
+        # step reduces a pair, and every active pair is reduced once (or kept
+        # as a residual)
+        assert len(tr) == res.steps
+        if ref.n_stuck == 0:
+            assert res.steps == rounds
+        assert np.all(tr > 0)
+        assert int(tr.sum()) == ref.interactions + ref.n_stuck
+        assert int(tr.max()) == res.max_frontier
+
+
+def test_parallelism_of_the_algae_system():
+    # generation n of A -> AB, B -> A: the widest step of our encoding is set
+    # by the string lengths, a Fibonacci sequence; the trace grows with n
+    rules = nets.algae_rules()
+    peaks = [int(P.parallelism(rules, nets.algae_net(n)).max()) for n in (10, 14, 18)]
+    assert peaks[0] < peaks[1] < peaks[2]
