@@ -472,6 +472,8 @@ def main():
                 args.max_resident = cfg.pop("max_resident")
             extra = cfg
             log(f"tuned: {tuned}")
+        else:
+            log("no tuned entry for this workload and device: library defaults")
     if args.pipeline:
         return bench_pipeline(args, P, R, net_list, workload, used_a, used_n, inter, steps, torch)
     h = P.batch_load(R, net_list, agent_caps=used_a + 64, name_caps=used_n + 64)
@@ -557,15 +559,15 @@ def main():
             if what is None:
                 what = f"Mul(S^{net.meta['a']} Z, S^{net.meta['b']} Z), seed 0"
             log(f"single net {key}")
-            cfg = {}
+            best = None
             if not args.no_tuned:
                 from paper_1404_0076_amd import autotune
                 best = autotune.lookup([net], autotune.SINGLE_SPACE)
-                cfg = dict(best["config"]) if best else {}
+            cfg = dict(best["config"]) if best else {}
             wg1 = cfg.pop("wg_size", 1024) or 1024
             rec = time_single(P, R, net, wg=wg1, **cfg)
             rec["workload"] = what
-            rec["tuned"] = bool(cfg)
+            rec["tuned"] = best is not None
             singles[key] = rec
         out["single_net_configs"] = singles
         out["single_net"] = dict(singles["mul"])

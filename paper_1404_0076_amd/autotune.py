@@ -106,10 +106,17 @@ def _store(path, key, value):
     os.replace(tmp, path)
 
 
-def key_for(net_list, space) -> str:
+def device_signature() -> str:
+    """The device a tuned entry holds for: ISA and compute-unit count (the
+    marketing name is not reported the same way on every host and under
+    every tool)."""
     import torch
-    dev = torch.cuda.get_device_name(0)
-    return f"{dev}/{workload_signature(net_list)}/{len(net_list)}/{space_signature(space)}"
+    p = torch.cuda.get_device_properties(0)
+    return f"{p.gcnArchName.split(':')[0]}x{p.multi_processor_count}"
+
+
+def key_for(net_list, space) -> str:
+    return f"{device_signature()}/{workload_signature(net_list)}/{len(net_list)}/{space_signature(space)}"
 
 
 def lookup(net_list, space, path: str = TUNED) -> Optional[Dict]:

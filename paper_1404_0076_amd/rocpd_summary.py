@@ -2,13 +2,15 @@
 
     python -m paper_1404_0076_amd.rocpd_summary trace  DIR   [--kernel NAME] [--last N]
     python -m paper_1404_0076_amd.rocpd_summary counters DIR [--kernel NAME] [--last N]
+    python -m paper_1404_0076_amd.rocpd_summary phases DIR
     python -m paper_1404_0076_amd.rocpd_summary hbm --fetch DIR --write DIR
         --copy-fetch DIR --copy-write DIR --copy-bytes N --bench-json FILE --sources-hash H
 
 ``trace``: per-kernel calls / total / average duration from a --kernel-trace
 run, plus the last N dispatches of the selected kernel.  ``counters``: the
 per-dispatch value of every collected counter (summed over its instances) for
-the selected kernel's last N dispatches.  ``hbm``: HBM bytes per launch of the
+the selected kernel's last N dispatches.  ``phases``: the paper-pipeline
+ablation's kernel time split into its loop's phases.  ``hbm``: HBM bytes per launch of the
 bench's reduce kernel from one FETCH_SIZE run and one WRITE_SIZE run, each
 scaled by what the same counter reads for a plain device copy of known size;
 the output carries the meta lines (kernel source hash, workload key, bytes per
@@ -115,9 +117,69 @@ def hbm(a):
     return "\n".join(out)
 
 
+# kernels of the paper-pipeline ablation that open a phase of its loop; the
+# primitives' own scan and reduction kernels belong to the phase that launched
+# them (the latest one opened)
+_PHASE_OPEN = (("k_pp_need", "int"), ("KeepIfNot", "filter"), ("k_pp_key", "com: sort"),
+               ("RunHead", "com: reduce by key"))
+_PHASES = ("int", "filter", "com: sort", "com: reduce by key", "copies and fills", "other")
+
+
+def _phase_of(name, cur):
+    for mark, ph in _PHASE_OPEN:
+        if mark in name:
+            return ph, ph
+    if "k_pp_int" in name:
+        return "int", "int"
+    if "k_rs_" in name:
+        return "com: sort", cur
+    if "k_tile_" in name:
+        return cur or "other", cur
+    if "copyBuffer" in name or "fillBuffer" in name:
+        return "copies and fills", cur
+    return "other", cur
+
+
+def phases(path):
+    """Kernel time of the paper pipeline's loop split by phase: int (need,
+    allocation scan, the interaction kernel), filter (dummy removal), com
+    (key, radix sort; reduce by key), and the copies and fills between them
+    (counts to the host, list moves).  The net engine's own launches in the
+    same process (sizing runs) are left out."""
+    out = []
+    for db in _dbs(path):
+        con = sqlite3.connect(db)
+        tot = dict.fromkeys(_PHASES, 0.0)
+        calls = dict.fromkeys(_PHASES, 0)
+        int_kernel = 0.0
+        cur = ""
+        for name, dur in con.execute("select name, duration from kernels order by start"):
+            if "inet_grid" in name or "inet_static" in name or "k_jump" in name \
+                    or "k_reset" in name or "k_zero" in name:
+                continue
+            ph, cur = _phase_of(name, cur)
+            tot[ph] += dur / 1e6
+            calls[ph] += 1
+            if "k_pp_int" in name:
+                int_kernel += dur / 1e6
+        all_ms = sum(tot.values())
+        out.append(f"# {os.path.basename(db)}: paper-pipeline kernel time by phase")
+        out.append(f"{'phase':22s} {'dispatches':>10s} {'ms':>10s} {'share':>7s}")
+        for ph in _PHASES:
+            out.append(f"{ph:22s} {calls[ph]:10d} {tot[ph]:10.3f} {tot[ph] / max(all_ms, 1e-9):7.1%}")
+        out.append(f"{'total':22s} {sum(calls.values()):10d} {all_ms:10.3f}")
+        out.append(f"interaction kernel alone (k_pp_int): {int_kernel:.3f} ms = "
+                   f"{int_kernel / max(all_ms, 1e-9):.2%} of the loop's kernel time")
+        if int_kernel > 0:
+            out.append(f"filter / interaction kernel = {tot['filter'] / int_kernel:.2f}; "
+                       f"(filter + com) / interaction kernel = "
+                       f"{(tot['filter'] + tot['com: sort'] + tot['com: reduce by key']) / int_kernel:.2f}")
+    return "\n".join(out)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["trace", "counters", "hbm"])
+    ap.add_argument("mode", choices=["trace", "counters", "hbm", "phases"])
     ap.add_argument("path", nargs="?", default="")
     ap.add_argument("--kernel", default="")
     ap.add_argument("--last", type=int, default=5)
@@ -133,6 +195,8 @@ def main(argv=None):
         print(hbm(a))
     elif a.mode == "trace":
         print(trace(a.path, a.kernel, a.last))
+    elif a.mode == "phases":
+        print(phases(a.path))
     else:
         print(counters(a.path, a.kernel, a.last))
 

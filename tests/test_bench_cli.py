@@ -23,3 +23,25 @@ def test_kernel_hash_names_the_kernel_sources():
     assert r.returncode == 0
     h = r.stdout.strip()
     assert len(h) == 16 and int(h, 16) >= 0
+
+
+def test_tuned_table_matches_the_search_spaces():
+    """Every committed tuned entry names a device (ISA x compute units), a
+    workload, a net count and one of the tuner's current search spaces, and
+    its configuration sets only knobs of that space to values it searches."""
+    import json
+    sys.path.insert(0, ROOT)
+    from paper_1404_0076_amd import autotune
+    with open(autotune.TUNED) as f:
+        table = json.load(f)
+    assert table
+    spaces = {autotune.space_signature(sp): sp for sp in (autotune.BATCH_SPACE, autotune.SINGLE_SPACE)}
+    for key, entry in table.items():
+        dev, sig, n, space = key.split("/", 3)
+        assert dev.startswith("gfx") and "x" in dev
+        assert len(sig) == 16 and int(n) >= 1
+        assert space in spaces, key
+        allowed = dict(spaces[space])
+        for k, v in entry["config"].items():
+            assert v in allowed[k], (key, k, v)
+        assert entry["seconds"] > 0
