@@ -145,9 +145,10 @@ typedef struct {
                                load-time compiled engine, one code object
                                per value)                                  */
   int32_t grid;             /* a handle holding one net, engine 3: 0 the
-                               multi-workgroup engine over every workgroup
-                               that can be resident; > 0 over at most this
-                               many; -1 one workgroup only.  Workgroup 0
+                               multi-workgroup engine over one workgroup per
+                               compute unit; > 0 over at most this many (and
+                               at most one per compute unit); -1 one
+                               workgroup only.  Workgroup 0
                                steps the net alone while at most grid_hi
                                pairs are active; above that the steps are
                                shared by ceil(active / grid_ppw) workgroups

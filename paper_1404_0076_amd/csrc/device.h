@@ -558,7 +558,9 @@ template <>
 struct Ctr<CM_GRID> {
   int *agent_top, *name_top, *nstuck, *status;  // global (the net's state)
   int *next;                                    // LDS: entries in the tile
-  int *spill_next;                              // global: entries of the next frontier
+  int *lerr;                                    // LDS: an error in this step
+  unsigned long long *spill_next;  // global: entries of all shared steps' frontiers
+  unsigned long long base;         // *spill_next when this step began
   __device__ __forceinline__ int take(int *p, int n) {
     int b = 0;
     if (__lane_id() == 0) b = gadd(p, n);
@@ -569,8 +571,15 @@ struct Ctr<CM_GRID> {
     if (__lane_id() == 0) b = atomicAdd(next, n);
     return __builtin_amdgcn_readfirstlane(b);
   }
-  // n entries past the LDS tile, straight into the global next frontier
-  __device__ __forceinline__ int spill(int n) { return take(spill_next, n); }
+  // n entries past the LDS tile, straight into the global next frontier (the
+  // index returned is relative to the step's frontier)
+  __device__ __forceinline__ int spill(int n) {
+    unsigned long long b = 0;
+    if (__lane_id() == 0)
+      b = __hip_atomic_fetch_add(spill_next, (unsigned long long)n, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_amdgcn_readfirstlane((int)(b - base));
+  }
   __device__ __forceinline__ int stuck(int n) { return take(nstuck, n); }
   __device__ __forceinline__ void agents_names(int na, int nn, int &ba, int &bn) {
     int a = 0, b = 0;
@@ -582,11 +591,15 @@ struct Ctr<CM_GRID> {
     bn = __builtin_amdgcn_readfirstlane(b);
   }
   __device__ __forceinline__ void fail_uniform(int lane, int lead) {
-    if (lane == lead) gstore(status, ST_ENOMEM);
+    if (lane == lead) {
+      gstore(status, ST_ENOMEM);
+      *lerr = 1;
+    }
   }
   __device__ __forceinline__ void fail(bool nomem, bool internal) {
     if (internal) gstore(status, ST_EINTERNAL);
     else if (nomem) gstore(status, ST_ENOMEM);
+    if (internal || nomem) *lerr = 1;
   }
 };
 
@@ -1032,6 +1045,53 @@ __device__ __forceinline__ bool grid_sync(GridCtl *ctl, int G, int &seen, unsign
   return ok;
 }
 
+// an epoch entry of the multi-workgroup engine
+__device__ __forceinline__ unsigned long long ent_pack(int epoch, bool err, int count) {
+  return ((unsigned long long)(unsigned)epoch << 32) | (err ? 0x80000000ull : 0ull) |
+         (unsigned long long)(unsigned)(count & 0x7fffffff);
+}
+
+// wave 0 of a workgroup: wait until all G entries of the epoch are posted;
+// their new-pair counts summed and error bits or'ed (the same values in every
+// lane).  False on give-up after `timeout` wall-clock ticks without progress
+// (a missing entry and no change of the heartbeat word).  Polls back off from
+// tens of nanoseconds to microseconds the longer the wait lasts.
+__device__ __forceinline__ bool wait_entries(GridCtl *ctl, int G, int epoch,
+                                             unsigned long long timeout, int &sum, bool &err) {
+  const int lane = __lane_id();
+  const unsigned long long *ent = ctl->ent[epoch & 1];
+  unsigned long long t0 = wall_clock64();
+  int hb = gload(&ctl->heartbeat);
+  for (int polls = 0;; polls++) {
+    int s = 0;
+    bool e = false, all = true;
+    for (int w = lane; w < G; w += 64) {
+      const unsigned long long v =
+          __hip_atomic_load(&ent[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      all = all && (int)(v >> 32) == epoch;
+      s += (int)(v & 0x7fffffffull);
+      e = e || (v & 0x80000000ull) != 0;
+    }
+    if (!ballot(!all)) {
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+      sum = s;
+      err = ballot(e) != 0;
+      return true;
+    }
+    const int h = gload(&ctl->heartbeat);
+    const unsigned long long t = wall_clock64();
+    if (h != hb) {
+      hb = h;
+      t0 = t;
+    } else if (t - t0 > timeout) {
+      return false;
+    }
+    if (polls < 256) __builtin_amdgcn_s_sleep(1);
+    else if (polls < 4096) __builtin_amdgcn_s_sleep(32);
+    else __builtin_amdgcn_s_sleep(127);
+  }
+}
+
 // pointer jumping over one net's cells by one workgroup (`flag`: an LDS word)
 template <int WG>
 __device__ __forceinline__ void jump_net(gint *__restrict__ bind, int n_cells, int *flag) {
@@ -1456,13 +1516,16 @@ __device__ __forceinline__ void reduce_body(const NetDesc *__restrict__ descs,
 // queue), runs the same pass as the one-workgroup engine with the heap tops
 // and status as agent-scope atomics in the net's state, stages its new active
 // pairs in its LDS tile and appends them to the next frontier with one
-// agent-scope atomic.  Steps are separated by a barrier over the launch:
-// agent-scope release before arriving, acquire after leaving, so that agent
-// records, name cells and queue entries written in a step are seen by every
-// workgroup in the next (the name-cell exchanges themselves are agent-scope
-// atomics).  Every wait at the barrier gives up after kp.timeout wall-clock
-// ticks without progress (a new epoch, or workgroup 0's step count moving),
-// setting ST_ETIMEDOUT, so the kernel always ends.
+// agent-scope atomic.  Epochs (a run of workgroup 0 alone, or one shared
+// step) end when every workgroup of the launch has posted its entry: an
+// agent-scope release before posting, acquire after all entries are seen, so
+// that agent records, name cells and queue entries written in an epoch are
+// seen by every workgroup in the next (the name-cell exchanges themselves are
+// agent-scope atomics).  Every workgroup takes the next epoch's decision from
+// the same inputs (the entries, and the state workgroup 0 left after a run
+// alone), so all take the same one.  Every wait gives up after kp.timeout
+// wall-clock ticks without progress (all entries posted, or workgroup 0's
+// step count moving), setting ST_ETIMEDOUT, so the kernel always ends.
 
 // logical index of block b of G: blocks are handed to the XCDs in turn
 // (block b runs on XCD b % 8), so logical indices run through one XCD's
@@ -1481,6 +1544,7 @@ __device__ __forceinline__ void grid_body(const NetDesc *__restrict__ descs,
                                           unsigned max_steps, int flags, const KParams &kp) {
   extern __shared__ int s_rules[];
   __shared__ EngineLds<QCAP> S;
+  __shared__ unsigned long long s_base;
   const RuleView RV = load_rules<WG, QCAP>(g_rules, ns, nr, s_rules);
   const NetDesc D = descs[0];
   NetState *st = D.st;
@@ -1492,14 +1556,12 @@ __device__ __forceinline__ void grid_body(const NetDesc *__restrict__ descs,
   gint *const bind = (gint *)D.bind;
   gint2 *const stuck = (gint2 *)D.stuck;
   const int lo = kp.grid_lo, hi = kp.grid_hi > kp.grid_lo ? kp.grid_hi : kp.grid_lo;
+  const int ppw = kp.grid_ppw > 0 ? kp.grid_ppw : WG;
   unsigned rc_lane = 0;
   int loops_lane = 0;
-  int seen = 0;
-  // epoch 0: workgroup 0 steps the net alone (linking the initial equations
+  // epoch 1: workgroup 0 steps the net alone (linking the initial equations
   // on the first launch) until it widens or ends
-  bool part = me == 0;
-  int mode = GM_NARROW;
-  unsigned stop = 0;  // absolute step budget (workgroup 0 only)
+  unsigned stop = 0;  // absolute step budget (workgroup 0: every thread; others: thread 0)
   if (me == 0) {
     const unsigned steps0 = st->steps;
     stop = (max_steps > 0xffffffffu - steps0) ? 0xffffffffu : steps0 + max_steps;
@@ -1507,45 +1569,70 @@ __device__ __forceinline__ void grid_body(const NetDesc *__restrict__ descs,
     engine_net<WG, QCAP, 3, MAXL, true, TRACE, SOLO_MAX>(S, D, RV, stop, 0, hi, kp,
                                                          &ctl->heartbeat);
   }
+  int epoch = 1, mode = GM_NARROW;
+  int count = 0;  // new active pairs of this workgroup in a GRID epoch (its entry)
+  // thread 0's view of the net, the same in every workgroup: active pairs of
+  // the coming GRID step, their queue, steps done before it, ctl->next before it
+  int n = 0, cur = 0;
+  unsigned steps = 0;
+  unsigned long long base = 0;
+  int maxf = 0;  // widest frontier (workgroup 0, thread 0)
   for (;;) {
-    // ---- barrier between epochs
+    // ---- post this workgroup's entry for the epoch, then read everyone's
     __syncthreads();
     if (tid == 0) {
-      bool ok = true;
-      if (part) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const int target = seen == 0 ? 1 : gload(&ctl->target);
-        if (gadd(&ctl->arrive, 1) == target - 1) {
-          // the last to arrive decides the next epoch
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-          int n, cur, status;
-          unsigned steps;
-          const unsigned stp = ctl->stop;
-          if (mode == GM_GRID) {
-            n = gload(&ctl->next);
-            cur = ctl->cur ^ 1;
-            steps = ctl->steps + 1;
-            const int done_n = ctl->n;
-            if (done_n > st->max_frontier) st->max_frontier = done_n;
-            if constexpr (TRACE)
-              if (D.trace && ctl->steps < (unsigned)D.trace_cap) D.trace[ctl->steps] = done_n;
-          } else {
-            n = st->frontier;
-            cur = st->parity;
-            steps = st->steps;
-            if (st->phase == PHASE_DONE) n = 0;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      const bool err = mode == GM_GRID && S.status != 0;
+      __hip_atomic_store(&ctl->ent[epoch & 1][me], ent_pack(epoch, err, count),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (tid < 64) {
+      int sum = 0;
+      bool err = false;
+      const bool ok = wait_entries(ctl, G, epoch, kp.timeout, sum, err);
+      if (tid == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        int next_mode = GM_DONE, g = 1;
+        if (!ok) {
+          gstore(&ctl->gave_up, 1);
+          gstore(&st->status, ST_ETIMEDOUT);
+          next_mode = -1;
+        } else if (mode == GM_NARROW) {
+          // workgroup 0 left the net's state as the one-workgroup engine does
+          n = st->phase == PHASE_DONE ? 0 : st->frontier;
+          cur = st->parity;
+          steps = st->steps;
+          stop = ctl->stop;
+          if (me == 0) maxf = st->max_frontier;
+          int status = gload(&st->status);
+          // a give-up by a workgroup that waited for this run ends the launch
+          // with it (workgroup 0's own bookkeeping may have written over the
+          // status); a give-up in a shared step stalls the next one, whose
+          // waits then give up too
+          if (gload(&ctl->gave_up)) {
+            status = ST_ETIMEDOUT;
+            if (me == 0) gstore(&st->status, ST_ETIMEDOUT);
           }
-          // a give-up recorded by any workgroup ends the launch with it
-          // (workgroup 0's own bookkeeping may have written over the status)
-          if (gload(&ctl->gave_up)) gstore(&st->status, ST_ETIMEDOUT);
-          status = gload(&st->status);
-          int next_mode, g = 1;
-          if (n == 0 || status < 0 || steps >= stp) {
-            next_mode = GM_DONE;
-            if (mode == GM_GRID) {
-              // the net's state as the one-workgroup engine leaves it
+          if (!(n == 0 || status < 0 || steps >= stop)) next_mode = n <= lo ? GM_NARROW : GM_GRID;
+        } else {
+          // a shared step ended: `sum` new active pairs in the other queue
+          const int done_n = n;
+          base += (unsigned long long)sum;
+          n = sum;
+          cur ^= 1;
+          if (me == 0) {
+            if (done_n > maxf) maxf = done_n;
+            if constexpr (TRACE)
+              if (D.trace && steps < (unsigned)D.trace_cap) D.trace[steps] = done_n;
+          }
+          steps++;
+          if (n == 0 || err || steps >= stop) {
+            if (me == 0) {
+              // the net's state as the one-workgroup engine leaves it (an
+              // error status is already there)
+              st->max_frontier = maxf;
               st->steps = steps;
-              if (status >= 0) {
+              if (!err) {
                 if (n == 0) {
                   st->phase = PHASE_DONE;
                   st->frontier = 0;
@@ -1560,64 +1647,53 @@ __device__ __forceinline__ void grid_body(const NetDesc *__restrict__ descs,
             }
           } else if (n <= lo) {
             next_mode = GM_NARROW;
-            st->phase = PHASE_RUN;
-            st->parity = cur;
-            st->frontier = n;
-            st->steps = steps;
+            if (me == 0) {
+              st->max_frontier = maxf;
+              st->phase = PHASE_RUN;
+              st->parity = cur;
+              st->frontier = n;
+              st->steps = steps;
+            }
           } else {
             next_mode = GM_GRID;
-            const int ppw = kp.grid_ppw > 0 ? kp.grid_ppw : WG;
-            g = (n + ppw - 1) / ppw;
-            if (g > G) g = G;
-            if (g < 1) g = 1;
           }
-          ctl->mode = next_mode;
-          ctl->n = n;
-          ctl->cur = cur;
-          ctl->g = g;
-          ctl->target = next_mode == GM_GRID ? g : 1;
-          ctl->steps = steps;
-          gstore(&ctl->next, 0);
-          gstore(&ctl->arrive, 0);
-          __hip_atomic_store(&ctl->gen, seen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-          ok = wait_epoch(ctl, seen, kp.timeout);
         }
-      } else {
-        ok = wait_epoch(ctl, seen, kp.timeout);
+        if (next_mode == GM_GRID) {
+          g = (n + ppw - 1) / ppw;
+          if (g > G) g = G;
+          if (g < 1) g = 1;
+        }
+        S.bcast[0] = next_mode;
+        S.bcast[1] = n;
+        S.bcast[2] = cur;
+        S.bcast[3] = g;
+        s_base = base;
       }
-      if (!ok) {
-        gstore(&ctl->gave_up, 1);
-        gstore(&st->status, ST_ETIMEDOUT);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      S.bcast[0] = ok ? ctl->mode : -1;
-      S.bcast[1] = ctl->n;
-      S.bcast[2] = ctl->cur;
-      S.bcast[3] = ctl->g;
-      S.bcast[4] = ctl->gen;
     }
     __syncthreads();
     mode = S.bcast[0];
     if (mode < 0 || mode == GM_DONE) break;
-    seen = S.bcast[4];
+    epoch++;
+    count = 0;
     if (mode == GM_NARROW) {
-      part = me == 0;
-      if (part)
+      if (me == 0)
         engine_net<WG, QCAP, 3, MAXL, true, TRACE, SOLO_MAX>(S, D, RV, stop, 0, hi, kp,
                                                              &ctl->heartbeat);
       continue;
     }
     // ---- one parallel step shared by the first g workgroups
-    const int n = S.bcast[1], cur = S.bcast[2], g = S.bcast[3];
-    part = me < g;
-    if (!part) continue;
-    const int per = (n + g - 1) / g;
+    const int sn = S.bcast[1], scur = S.bcast[2], g = S.bcast[3];
+    const unsigned long long sbase = s_base;
+    if (tid == 0) {
+      S.cnt[0] = 0;
+      S.status = 0;
+    }
+    if (me >= g) continue;
+    const int per = (sn + g - 1) / g;
     const int i0 = me * per;
-    const int i1 = i0 + per < n ? i0 + per : n;
-    const gint2 *cq_g = (const gint2 *)(cur ? D.queue1 : D.queue0);
-    gint2 *nq_g = (gint2 *)(cur ? D.queue0 : D.queue1);
-    if (tid == 0) S.cnt[0] = 0;
+    const int i1 = i0 + per < sn ? i0 + per : sn;
+    const gint2 *cq_g = (const gint2 *)(scur ? D.queue1 : D.queue0);
+    gint2 *nq_g = (gint2 *)(scur ? D.queue0 : D.queue1);
     __syncthreads();
     Ctr<CM_GRID> C;
     C.agent_top = &st->agent_top;
@@ -1625,9 +1701,11 @@ __device__ __forceinline__ void grid_body(const NetDesc *__restrict__ descs,
     C.nstuck = &st->n_stuck;
     C.status = &st->status;
     C.next = &S.cnt[0];
+    C.lerr = &S.status;
     C.spill_next = &ctl->next;
-    for (int base = i0; base < i1; base += WG) {
-      const int i = base + tid;
+    C.base = sbase;
+    for (int base_i = i0; base_i < i1; base_i += WG) {
+      const int i = base_i + tid;
       const bool valid = i < i1;
       const Pair rx = valid ? unpk(*at2((gint2 *)cq_g, (unsigned)i)) : mkpair(0, 0);
       const v4i ra = *rec(agent, (unsigned)rx.x), rb = *rec(agent, (unsigned)rx.y);
@@ -1638,8 +1716,14 @@ __device__ __forceinline__ void grid_body(const NetDesc *__restrict__ descs,
     }
     // the workgroup's new active pairs from its LDS tile to the next frontier
     __syncthreads();
-    const int tile = S.cnt[0] < QCAP ? S.cnt[0] : QCAP;
-    if (tid == 0) S.bcast[5] = tile ? gadd(&ctl->next, tile) : 0;
+    const int total = S.cnt[0];
+    const int tile = total < QCAP ? total : QCAP;
+    if (tid == 0)
+      S.bcast[5] = tile ? (int)(__hip_atomic_fetch_add(&ctl->next, (unsigned long long)tile,
+                                                       __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT) -
+                                sbase)
+                        : 0;
     __syncthreads();
     const int gb = S.bcast[5];
     bool over = false;
@@ -1647,7 +1731,11 @@ __device__ __forceinline__ void grid_body(const NetDesc *__restrict__ descs,
       if (gb + k < D.qcap) *at2(nq_g, (unsigned)(gb + k)) = pk(S.q[0][k].x, S.q[0][k].y);
       else over = true;
     }
-    if (over) gstore(&st->status, ST_ENOMEM);
+    if (over) {
+      gstore(&st->status, ST_ENOMEM);
+      S.status = ST_ENOMEM;
+    }
+    count = total;
   }
   // this workgroup's interactions per rule and dropped loops of its shared steps
   gu64 *per_rule = (gu64 *)D.per_rule;

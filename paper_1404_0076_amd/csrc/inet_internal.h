@@ -110,30 +110,32 @@ enum { ST_OK = 0, ST_STUCK = 1, ST_ENOMEM = -2, ST_ELIMIT = -3, ST_EINTERNAL = -
        ST_ETIMEDOUT = -9 };
 
 // Control block of the multi-workgroup engine of one net (global memory,
-// cleared before each launch).  The launch runs in epochs separated by a
-// barrier: in a NARROW epoch workgroup 0 steps the net alone; in a GRID epoch
-// the g workgroups of lowest logical index share one parallel step.  The
-// last workgroup to arrive decides the next epoch and publishes it by
-// bumping `gen`.  Each group of words sits on its own 128-byte line.
+// cleared before each launch).  The launch runs in epochs: in a NARROW epoch
+// workgroup 0 steps the net alone; in a GRID epoch the g workgroups of lowest
+// logical index share one parallel step.  An epoch ends when every workgroup
+// has posted its entry for it (epoch number, error bit, new active pairs);
+// each workgroup then reads all entries and takes the same decision about the
+// next epoch, so no workgroup has to publish it.  The entries alternate
+// between two arrays by epoch parity: no workgroup can be two epochs ahead of
+// another, since every workgroup posts in every epoch.  Each group of scalar
+// words sits on its own 128-byte line; the pointer-jumping pass uses the
+// arrive / gen barrier.
 enum { GM_NARROW = 0, GM_GRID = 1, GM_DONE = 2 };
+constexpr int kGridMax = 2048;  // workgroups of one multi-workgroup launch, at most
 struct GridCtl {
-  int32_t arrive;  // arrivals in the current epoch
+  int32_t arrive;  // pointer jumping: arrivals in the current round
   int32_t pad0[31];
-  int32_t gen;        // epoch counter (bumped by the deciding workgroup)
+  int32_t gen;        // pointer jumping: round counter
   int32_t heartbeat;  // bumped by workgroup 0 while it steps alone
   int32_t pad1[30];
-  int32_t mode;    // GM_* of the current epoch
-  int32_t n;       // active pairs of the current (GRID) step, in queue `cur`
-  int32_t cur;     // queue holding them (0: queue0, 1: queue1)
-  int32_t g;       // participating workgroups (GRID)
-  int32_t target;  // arrivals that end the current epoch
-  uint32_t steps;  // steps done before the current epoch
-  uint32_t stop;   // step budget end (absolute)
+  uint32_t stop;     // step budget end (absolute), written by workgroup 0
   int32_t moved[2];  // pointer jumping: a cell moved in round r (moved[r & 1])
   int32_t gave_up;   // a workgroup gave up waiting (sticky)
-  int32_t pad2[22];
-  int32_t next;  // frontier entries appended in the current GRID step
-  int32_t pad3[31];
+  int32_t pad2[28];
+  unsigned long long next;  // frontier entries appended by all GRID steps so far
+  int32_t pad3[30];
+  // per epoch parity and workgroup: (epoch << 32) | (error << 31) | new pairs
+  unsigned long long ent[2][kGridMax];
 };
 
 // tunables of the reduction kernel (by value)

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -144,7 +145,7 @@ extern "C" int inet_reduce_noalloc(const inet_rules *rules, const int32_t *label
     const uint32_t ms = (left == 0 || left > kStepsPerLaunch) ? kStepsPerLaunch : (uint32_t)left;
     rc = launch_zero(d_counter, 1, stream);
     if (!rc) rc = launch_reduce(R, sh, 1, d_desc, d_order, 1, d_counter, d_rules, ms, 0, kp, stream);
-    if (!rc) rc = launch_zero((int32_t *)d_grid, (int)(sizeof(GridCtl) / 4), stream);
+    if (!rc) rc = launch_zero((int32_t *)d_grid, (int)(offsetof(GridCtl, ent) / 4), stream);
     if (!rc) rc = launch_jump_grid(d_desc, d_grid, kp.timeout, std::max(1, n_cu), stream);
     if (rc) return rc;
     HIPCHK(hipMemcpyAsync(&st, d_state, sizeof(NetState), hipMemcpyDeviceToHost, stream));

@@ -256,7 +256,7 @@ __global__ __launch_bounds__(BLOCK) void k_rs_scatter(const uint32_t *__restrict
   __shared__ uint32_t run[RADIX];        // elements of each digit placed so far in this tile
   __shared__ uint32_t wcnt[WAVES][RADIX];  // this round's count of each digit per wave
   __shared__ uint32_t start[RADIX];      // first output position of each digit for this tile
-  const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
+  const int tid = threadIdx.x, w = tid >> 6;
   {
     const size_t j = (size_t)tid * gridDim.x + blockIdx.x;
     start[tid] = incl[j] - hist[j];

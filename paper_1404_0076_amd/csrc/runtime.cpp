@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cstdint>
 #include <cstring>
 #include <new>
@@ -371,9 +372,13 @@ static int grid_workgroups(const inet_net *h, const LaunchShape &sh, int *G) {
     return INET_EHIP;
   int rc = jit_grid_occupancy(h->rules, sh, &per_cu);
   if (rc) return rc;
-  // every workgroup must be resident at once (they wait for each other)
-  int g = std::max(1, per_cu) * std::max(1, n_cu);
+  // every workgroup must be resident at once (each posts an entry in every
+  // epoch and waits for all the others'): one per compute unit, which needs
+  // no more than the engine fitting on a compute unit at all
+  if (per_cu < 1) return INET_OK;
+  int g = std::max(1, n_cu);
   if (h->cfg.grid > 0) g = std::min(g, h->cfg.grid);
+  g = std::min(g, kGridMax);
   *G = g >= 2 ? g : 0;
   return INET_OK;
 }
@@ -408,7 +413,8 @@ static int enqueue_reduce(inet_net *h, hipStream_t stream, uint64_t max_steps, b
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return INET_EHIP;
-    rc = launch_zero((int32_t *)h->d_grid, (int)(sizeof(GridCtl) / 4), stream);
+    // the pointer-jumping barrier uses the scalar words only, not the entries
+    rc = launch_zero((int32_t *)h->d_grid, (int)(offsetof(GridCtl, ent) / 4), stream);
     if (!rc) rc = launch_jump_grid(h->d_descs, h->d_grid, kp.timeout, std::max(1, n_cu), stream);
     if (rc) return rc;
   }
