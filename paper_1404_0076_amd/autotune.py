@@ -38,10 +38,10 @@ BATCH_SPACE: List[Tuple[str, Tuple[int, ...]]] = [
 ]
 SINGLE_SPACE: List[Tuple[str, Tuple[int, ...]]] = [
     ("wg_size", (1024, 512, 256)),
-    ("grid", (0, -1, 64, 32)),
-    ("grid_hi", (2048, 1024, 4096, 8192)),
+    ("grid", (0, -1, 64, 32, 16)),
+    ("grid_hi", (2048, 1024, 512, 256, 4096)),
     ("grid_lo", (1024, 512, 256, 2048)),
-    ("grid_ppw", (0, 256, 512, 2048)),
+    ("grid_ppw", (0, 256, 512, 128, 2048)),
     ("qcap", (0, 2048, 8192)),
     ("solo_max", (64, 32, 128)),
 ]

@@ -24,6 +24,10 @@ EMPTY = 0x7FFFFFFF
 # shared step gives each workgroup about 48 pairs
 FORCED = dict(grid_lo=32, grid_hi=64, grid_ppw=48)
 ALWAYS = dict(grid_lo=1, grid_hi=1, grid_ppw=16)  # every step with two or more pairs is shared
+# the smallest LDS tile: a workgroup's new pairs of a shared step overflow it,
+# so the pairs past it go to the global queue and the tiles are flushed
+# behind them before the next step
+TILE = dict(grid_lo=32, grid_hi=64, grid_ppw=48, qcap=64)
 ONE_WG = dict(grid=-1)
 
 
@@ -51,7 +55,7 @@ SMALL_NETS = [nets.mul_net(30, 41), nets.fib_net(12), nets.config1_add_tree(3, 6
               nets.parse_net(nets.ARITH_SIG, "<r, q | S(r) = Z, Add(q, y) = Fib(y)>")]
 
 
-@pytest.mark.parametrize("cfg", [FORCED, ALWAYS], ids=["forced", "always"])
+@pytest.mark.parametrize("cfg", [FORCED, ALWAYS, TILE], ids=["forced", "always", "tile"])
 @pytest.mark.parametrize("wg", [256, 1024])
 def test_grid_small_nets(cfg, wg):
     for net in SMALL_NETS + [n for _, n in small_exprs(8, 12, 5, 400_000)]:
@@ -60,7 +64,7 @@ def test_grid_small_nets(cfg, wg):
     assert grid_used(R, nets.mul_net(120, 90), wg_size=wg, **cfg).max_frontier > 64
 
 
-@pytest.mark.parametrize("cfg", [FORCED, ALWAYS, ONE_WG], ids=["forced", "always", "one"])
+@pytest.mark.parametrize("cfg", [FORCED, ALWAYS, ONE_WG, TILE], ids=["forced", "always", "one", "tile"])
 def test_grid_steps_equal_oracle_rounds(cfg):
     # a shared step reduces exactly the active pairs present after com has
     # run to closure, like a one-workgroup step: maximal parallel rounds
@@ -230,7 +234,7 @@ def test_jump_in_batch_engines():
 
 @pytest.mark.slow
 @pytest.mark.parametrize("seed", range(5))
-@pytest.mark.parametrize("cfg", [{}, FORCED], ids=["default", "forced"])
+@pytest.mark.parametrize("cfg", [{}, FORCED, TILE], ids=["default", "forced", "tile"])
 def test_grid_config2_mul_full(seed, cfg):
     net = nets.config2_mul(seed)
     a, b = net.meta["a"], net.meta["b"]
@@ -257,7 +261,7 @@ def test_grid_fib27_and_add_tree(cfg):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("cfg", [{}, FORCED, ONE_WG], ids=["default", "forced", "one"])
+@pytest.mark.parametrize("cfg", [{}, FORCED, ONE_WG, TILE], ids=["default", "forced", "one", "tile"])
 def test_grid_algae_27(cfg):
     rules = nets.algae_rules()
     net = nets.algae_net(27)
