@@ -581,14 +581,45 @@ struct Ctr<CM_GRID> {
     return __builtin_amdgcn_readfirstlane((int)(b - base));
   }
   __device__ __forceinline__ int stuck(int n) { return take(nstuck, n); }
+  // agents and names for a whole wave.  When many workgroups share the step
+  // and most waves of this one have pairs (`collective`, the same in every
+  // wave) they are reserved for
+  // the whole workgroup at once: the waves' needs are summed in LDS and one
+  // thread takes them from the net's heap tops (two agent-scope atomics per
+  // workgroup instead of two per wave, all on the same two words; every wave
+  // then calls this, across two workgroup barriers).  Otherwise each wave
+  // with a need takes its own.
+  int *wneed, *wbase;  // LDS: needs of the waves so far [2], the workgroup's bases [2]
+  bool collective;
   __device__ __forceinline__ void agents_names(int na, int nn, int &ba, int &bn) {
-    int a = 0, b = 0;
-    if (__lane_id() == 0) {
-      if (na) a = gadd(agent_top, na);
-      if (nn) b = gadd(name_top, nn);
+    if (!collective) {
+      int a = 0, b = 0;
+      if (__lane_id() == 0) {
+        if (na) a = gadd(agent_top, na);
+        if (nn) b = gadd(name_top, nn);
+      }
+      ba = __builtin_amdgcn_readfirstlane(a);
+      bn = __builtin_amdgcn_readfirstlane(b);
+      return;
     }
-    ba = __builtin_amdgcn_readfirstlane(a);
-    bn = __builtin_amdgcn_readfirstlane(b);
+    int oa = 0, on = 0;
+    if (__lane_id() == 0) {
+      if (na) oa = atomicAdd(&wneed[0], na);
+      if (nn) on = atomicAdd(&wneed[1], nn);
+    }
+    oa = __builtin_amdgcn_readfirstlane(oa);
+    on = __builtin_amdgcn_readfirstlane(on);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int ta = wneed[0], tn = wneed[1];
+      wbase[0] = ta ? gadd(agent_top, ta) : 0;
+      wbase[1] = tn ? gadd(name_top, tn) : 0;
+      wneed[0] = 0;
+      wneed[1] = 0;
+    }
+    __syncthreads();
+    ba = wbase[0] + oa;
+    bn = wbase[1] + on;
   }
   __device__ __forceinline__ void fail_uniform(int lane, int lead) {
     if (lane == lead) {
@@ -803,7 +834,9 @@ __device__ __forceinline__ void pass_static(bool valid, int a, int b, int la, in
       need_a += rt::T[R][RT_NALLOC] * __popcll(gm);
       need_n += rt::T[R][RT_NFRESH] * __popcll(gm);
     });
-    if (need_a | need_n) C.agents_names(need_a, need_n, wa, wn);
+    bool call = (need_a | need_n) != 0;
+    if constexpr (CM == CM_GRID) call = call || C.collective;  // then every wave
+    if (call) C.agents_names(need_a, need_n, wa, wn);
   }
   // first walk: allocate, write the new agents, issue the exchanges
   for_rules<0>(rid, ballot(rid >= 0), [&](auto ic, unsigned long long gm) {
@@ -1119,6 +1152,7 @@ struct EngineLds {
   int cur;
   unsigned long long rc[MAXRULES];
   int bcast[8];    // values broadcast to the workgroup (multi-workgroup engine)
+  int wneed[2], wbase[2];  // multi-workgroup engine: the workgroup's heap reservation
 };
 
 // The rule table in LDS: rule_of[ns*ns] | templates[nr][RT_WORDS] | arity[ns]
@@ -1687,6 +1721,8 @@ __device__ __forceinline__ void grid_body(const NetDesc *__restrict__ descs,
     if (tid == 0) {
       S.cnt[0] = 0;
       S.status = 0;
+      S.wneed[0] = 0;
+      S.wneed[1] = 0;
     }
     if (me >= g) continue;
     const int per = (sn + g - 1) / g;
@@ -1704,9 +1740,14 @@ __device__ __forceinline__ void grid_body(const NetDesc *__restrict__ descs,
     C.lerr = &S.status;
     C.spill_next = &ctl->next;
     C.base = sbase;
+    C.wneed = S.wneed;
+    C.wbase = S.wbase;
     for (int base_i = i0; base_i < i1; base_i += WG) {
       const int i = base_i + tid;
       const bool valid = i < i1;
+      // one reservation per workgroup when many workgroups contend for the
+      // heap tops and at least half the lanes have a pair
+      C.collective = g >= 16 && 2 * (i1 - base_i) >= WG;
       const Pair rx = valid ? unpk(*at2((gint2 *)cq_g, (unsigned)i)) : mkpair(0, 0);
       const v4i ra = *rec(agent, (unsigned)rx.x), rb = *rec(agent, (unsigned)rx.y);
       int nha, nhb;
