@@ -234,7 +234,9 @@ def test_jump_in_batch_engines():
 
 @pytest.mark.slow
 @pytest.mark.parametrize("seed", range(5))
-@pytest.mark.parametrize("cfg", [{}, FORCED, TILE], ids=["default", "forced", "tile"])
+@pytest.mark.parametrize("cfg", [{}, FORCED, TILE,
+                                 dict(grid=16, grid_lo=2048, grid_hi=2048, grid_ppw=128, qcap=8192)],
+                         ids=["default", "forced", "tile", "tuned"])
 def test_grid_config2_mul_full(seed, cfg):
     net = nets.config2_mul(seed)
     a, b = net.meta["a"], net.meta["b"]
@@ -260,8 +262,14 @@ def test_grid_fib27_and_add_tree(cfg):
     assert_same(g, oracle_run(R, net), "grid add tree")
 
 
+# the benchmark's tuned shape: 64 workgroups of 512 lanes, full chunks, so
+# the heap reservation is taken once per workgroup
+ALGAE_TUNED = dict(wg_size=512, grid=64, grid_lo=256, grid_hi=1024, grid_ppw=256, qcap=8192)
+
+
 @pytest.mark.slow
-@pytest.mark.parametrize("cfg", [{}, FORCED, ONE_WG, TILE], ids=["default", "forced", "one", "tile"])
+@pytest.mark.parametrize("cfg", [{}, FORCED, ONE_WG, TILE, ALGAE_TUNED],
+                         ids=["default", "forced", "one", "tile", "tuned"])
 def test_grid_algae_27(cfg):
     rules = nets.algae_rules()
     net = nets.algae_net(27)
