@@ -32,7 +32,7 @@ TUNED = os.path.join(HERE, "tuned.json")
 BATCH_SPACE: List[Tuple[str, Tuple[int, ...]]] = [
     ("wg_size", (1024, 512, 256, 64)),
     ("engine", (3, 4, 2)),
-    ("max_resident", (0, 256, 128, 64)),
+    ("max_resident", (0, 256, 128, 64, 32, 16)),
     ("qcap", (0, 1024, 2048, 8192)),
     ("solo_max", (64, 32, 128, 256)),
 ]
