@@ -43,8 +43,8 @@ def trace(path, kernel, last):
             out.append(f"{name[:70]:70s} {calls:6d} {total / 1e3:10.3f} {avg:12.3f}")
         if kernel:
             rows = con.execute("select name, duration, grid_x, workgroup_x, lds_size, vgpr_count "
-                               "from kernels where name like ? order by start",
-                               (f"%{kernel}%",)).fetchall()
+                               "from kernels where instr(name, ?) > 0 order by start",
+                               (kernel,)).fetchall()
             out.append(f"last {min(last, len(rows))} dispatches of {kernel}: "
                        "duration_us grid workgroup lds vgpr")
             for name, dur, gx, wx, lds, vgpr in rows[-last:]:
@@ -58,8 +58,8 @@ def counters(path, kernel, last):
         con = sqlite3.connect(db)
         rows = con.execute(
             "select dispatch_id, kernel_name, counter_name, sum(value), grid_size, duration "
-            "from counters_collection where kernel_name like ? group by dispatch_id, counter_name "
-            "order by start", (f"%{kernel}%",)).fetchall()
+            "from counters_collection where instr(kernel_name, ?) > 0 "
+            "group by dispatch_id, counter_name order by start", (kernel,)).fetchall()
         out.append(f"# {os.path.basename(db)}: last {min(last, len(rows))} dispatches of {kernel}")
         out.append("  dispatch counter value(KiB for *_SIZE) grid duration_us")
         for d, name, cname, val, grid, dur in rows[-last:]:
@@ -73,8 +73,8 @@ def _counter_rows(path, kernel, counter):
         con = sqlite3.connect(db)
         rows += con.execute(
             "select dispatch_id, sum(value), duration from counters_collection "
-            "where kernel_name like ? and counter_name = ? group by dispatch_id order by start",
-            (f"%{kernel}%", counter)).fetchall()
+            "where instr(kernel_name, ?) > 0 and counter_name = ? group by dispatch_id order by start",
+            (kernel, counter)).fetchall()
     if not rows:
         raise SystemExit(f"no {counter} rows for {kernel!r} under {path}")
     return rows
