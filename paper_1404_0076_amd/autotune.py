@@ -45,11 +45,6 @@ SINGLE_SPACE: List[Tuple[str, Tuple[int, ...]]] = [
     ("qcap", (0, 2048, 8192)),
     ("solo_max", (64, 32, 128)),
 ]
-# kept for callers of the earlier grid search
-WIDTHS = (64, 128, 256, 512, 1024)
-ENGINES = (2, 3, 4)
-RESIDENTS = (0, 64, 128, 256)
-
 
 def workload_signature(net_list: Sequence) -> str:
     h = hashlib.sha256()
