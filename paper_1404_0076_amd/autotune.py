@@ -41,7 +41,7 @@ SINGLE_SPACE: List[Tuple[str, Tuple[int, ...]]] = [
     ("grid", (0, -1, 64, 32, 16)),
     ("grid_hi", (2048, 1024, 512, 256, 4096)),
     ("grid_lo", (1024, 512, 256, 2048)),
-    ("grid_ppw", (0, 256, 512, 128, 2048)),
+    ("grid_ppw", (0, 256, 512, 128, 64, 2048)),
     ("qcap", (0, 2048, 8192)),
     ("solo_max", (64, 32, 128)),
 ]
@@ -120,9 +120,13 @@ def lookup(net_list, space, path: str = TUNED) -> Optional[Dict]:
 
 
 def tune(rules, net_list: Sequence, agent_caps, name_caps, order=None, reps: int = 2,
-         space=None, cache: Optional[str] = CACHE, verbose: bool = False) -> Dict:
+         space=None, cache: Optional[str] = CACHE, verbose: bool = False,
+         passes: int = 2) -> Dict:
     """Best configuration for this workload: {"config": {...}, "seconds",
-    "trials"}; ``config`` holds every searched knob (set_config keywords)."""
+    "trials"}; ``config`` holds every searched knob (set_config keywords).
+    Coordinate descent: one knob at a time over its values, the others held at
+    their best so far, repeated over all knobs up to ``passes`` times (a pass
+    that changes nothing ends the search; a configuration is timed once)."""
     if space is None:
         space = BATCH_SPACE if len(net_list) > 1 else SINGLE_SPACE
     key = key_for(net_list, space)
@@ -136,22 +140,26 @@ def tune(rules, net_list: Sequence, agent_caps, name_caps, order=None, reps: int
     cur = {k: vals[0] for k, vals in space}
     trials = []
     best_t = None
-    for k, vals in space:
-        best_v = cur[k]
-        for v in vals:
-            cfg = dict(cur, **{k: v})
-            if any(t["config"] == cfg for t in trials):
-                t = next(t["seconds"] for t in trials if t["config"] == cfg)
-            elif not _valid(h, cfg):
-                continue
-            else:
-                t = _time(h, reps)
-                trials.append({"config": cfg, "seconds": t})
-                if verbose:
-                    print("autotune", trials[-1], flush=True)
-            if best_t is None or t < best_t:
-                best_t, best_v = t, v
-        cur[k] = best_v
+    for _ in range(max(1, passes)):
+        before = dict(cur)
+        for k, vals in space:
+            best_v = cur[k]
+            for v in vals:
+                cfg = dict(cur, **{k: v})
+                if any(t["config"] == cfg for t in trials):
+                    t = next(t["seconds"] for t in trials if t["config"] == cfg)
+                elif not _valid(h, cfg):
+                    continue
+                else:
+                    t = _time(h, reps)
+                    trials.append({"config": cfg, "seconds": t})
+                    if verbose:
+                        print("autotune", trials[-1], flush=True)
+                if best_t is None or t < best_t:
+                    best_t, best_v = t, v
+            cur[k] = best_v
+        if cur == before:
+            break
     h.free()
     best = {"config": cur, "seconds": best_t, "trials": trials}
     if cache:
