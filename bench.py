@@ -183,6 +183,11 @@ def measure_served(P, R, pool, caps, ref_counts, rate, duration, round_steps=256
     if loop == "native":
         srv = P.Server(R, 8192, 48 << 30)
         srv.set_config(wg_size=wg)
+        # a short untimed run first: the load-time compilation of the engine
+        # for this launch shape would otherwise stall the first round while
+        # arrivals queue up
+        srv.run(pool, np.zeros(64), np.arange(64) % len(pool), caps=caps,
+                round_steps=round_steps, time_limit=60.0, stream=torch.cuda.current_stream())
         res = srv.run(pool, arrivals, pick, caps=caps, round_steps=round_steps, time_limit=900.0,
                       stream=torch.cuda.current_stream())
         srv.free()
