@@ -168,7 +168,7 @@ def cpu_baseline_parallel(R, net_list):
 
 
 def measure_served(P, R, pool, caps, ref_counts, rate, duration, round_steps=256, wg=0,
-                   loop="native"):
+                   loop="native", round_scale=0):
     """Serve a Poisson stream (rate nets/s for duration s, seed 3) of requests
     drawn from ``pool`` with replacement (seed 4).  Latency = completion -
     arrival (queueing included); sustained rate = completed interactions over
@@ -182,7 +182,7 @@ def measure_served(P, R, pool, caps, ref_counts, rate, duration, round_steps=256
     import torch
     if loop == "native":
         srv = P.Server(R, 8192, 48 << 30)
-        srv.set_config(wg_size=wg)
+        srv.set_config(wg_size=wg, round_scale=round_scale)
         # a short untimed run first: the load-time compilation of the engine
         # for this launch shape would otherwise stall the first round while
         # arrivals queue up
@@ -238,7 +238,7 @@ def bench_serve(args, P, R, nets, torch, pool_ref=None, pool=None):
     if pool_ref is not None:
         ref, checked = pool_ref[1], "the oracle"
     rec = measure_served(P, R, pool, caps, ref, args.rate, args.duration, args.round_steps,
-                         args.wg, args.serve_loop)
+                         args.wg, args.serve_loop, args.round_scale)
     out = {
         "metric": METRIC, "value": rec["sustained"], "unit": "interactions/s",
         "n_gpus": 1, "steps": rec["rounds"], "warmup": 0,
@@ -247,7 +247,8 @@ def bench_serve(args, P, R, nets, torch, pool_ref=None, pool=None):
         "data": "synthetic",
         "config": {"workload": f"served: Poisson arrivals at {args.rate:g} nets/s for {args.duration:g} s "
                                f"from a pool of {len(pool)} nets (batch mix, seed 2)",
-                   "round_steps": args.round_steps, "requests": rec["requests"],
+                   "round_steps": args.round_steps, "round_scale": args.round_scale,
+                   "requests": rec["requests"],
                    "loop": args.serve_loop},
         "latency_ms": rec["latency_ms"],
         "offered_interactions_per_s": rec["offered"],
@@ -339,6 +340,9 @@ def main():
     ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals")
     ap.add_argument("--pool", type=int, default=65536, help="serve: request pool size")
     ap.add_argument("--round-steps", type=int, default=256, help="serve: step budget per round")
+    ap.add_argument("--round-scale", type=int, default=8,
+                    help="serve: a round's budget grows with the running nets per engine, up to "
+                         "this factor (inet_config.round_scale; 0: fixed rounds)")
     ap.add_argument("--serve-loop", default="native", choices=["native", "python"],
                     help="serve: the library's serving loop or the Python driver")
     ap.add_argument("--seed", type=int, default=0)
@@ -582,10 +586,12 @@ def main():
         rates = [float(x) for x in args.serve_rates.split(",") if x]
         out["served"] = {
             "workload": f"Poisson arrivals from a pool of {len(pool)} nets (batch mix, seed 2), "
-                        f"native serving loop, {args.round_steps} steps per round",
+                        f"native serving loop, {args.round_steps} steps per round "
+                        f"(up to {max(1, args.round_scale)}x under load)",
             "interactions_checked_against": "the sizing pass" if pool_ref is None else "the oracle",
             "rates": [measure_served(P, R, pool, caps, ref, rate, args.serve_duration,
-                                     args.round_steps) for rate in rates]}
+                                     args.round_steps, round_scale=args.round_scale)
+                      for rate in rates]}
         if pool_ref is not None:
             out["served"]["cpu_baseline"] = pool_ref[0]
     if not args.no_cpu_baseline:

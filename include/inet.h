@@ -167,6 +167,15 @@ typedef struct {
                                rest of a frontier lives in the net's global
                                queue); 0: by width, 512 for 64 lanes, 1024
                                for 128 and 256, 2048 for 512, 4096 for 1024 */
+  int32_t round_scale;      /* serving loop (inet_server_step,
+                               inet_server_run): a round's step budget is the
+                               caller's round_steps times the number of
+                               running nets per resident engine, rounded
+                               down, at least 1 and at most round_scale; 0 or
+                               1: round_steps.  Under load, when each engine
+                               already steps several nets per round, longer
+                               rounds cost few admissions but cut the rounds
+                               a long net needs                             */
 } inet_config;
 
 typedef struct inet_net inet_net;

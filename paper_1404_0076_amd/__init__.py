@@ -61,12 +61,13 @@ class _Config(ctypes.Structure):
                 ("solo_max", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("grid_lo", ctypes.c_int32), ("grid_hi", ctypes.c_int32),
                 ("grid_ppw", ctypes.c_int32), ("timeout_us", ctypes.c_int32),
-                ("qcap", ctypes.c_int32)]
+                ("qcap", ctypes.c_int32), ("round_scale", ctypes.c_int32)]
 
 
 # tunables of inet_config beyond wg_size / jump / max_resident / engine (all
 # 0 = the library's default; grid -1 keeps a single net on one workgroup)
-CONFIG_KEYS = ("solo_max", "grid", "grid_lo", "grid_hi", "grid_ppw", "timeout_us", "qcap")
+CONFIG_KEYS = ("solo_max", "grid", "grid_lo", "grid_hi", "grid_ppw", "timeout_us", "qcap",
+               "round_scale")
 
 
 def _config(wg_size, jump, max_resident, engine, extra) -> "_Config":

@@ -127,7 +127,7 @@ bool config_valid(const inet_config &c) {
   if (c.wg_size != 0 && !shape_supported(c.wg_size)) return false;
   if (c.max_resident < 0 || c.engine < 0 || c.engine > 4) return false;
   if (c.solo_max < 0 || c.grid < -1 || c.grid_lo < 0 || c.grid_hi < 0 || c.grid_ppw < 0 ||
-      c.timeout_us < 0)
+      c.timeout_us < 0 || c.round_scale < 0)
     return false;
   if (c.qcap != 0 && (c.qcap < 64 || c.qcap > 8192 || (c.qcap & (c.qcap - 1)))) return false;
   if (c.solo_max > 4096) return false;

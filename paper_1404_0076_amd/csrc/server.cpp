@@ -104,6 +104,19 @@ inet_server::Slot *slot_of(inet_server *s, int64_t ticket) {
   return &s->slots[it->second];
 }
 
+// a round's step budget: `steps`, or with round_scale set, `steps` times the
+// running nets per resident engine (at least 1, at most round_scale), so that
+// under load, when every engine already steps several nets in a round, a long
+// net needs fewer rounds
+uint32_t round_budget(const inet_config &cfg, uint32_t steps, int n, int grid) {
+  if (cfg.round_scale <= 1 || grid <= 0) return steps;
+  uint64_t k = (uint64_t)(n / grid);
+  if (k < 1) k = 1;
+  if (k > (uint64_t)cfg.round_scale) k = (uint64_t)cfg.round_scale;
+  const uint64_t b = (uint64_t)steps * k;
+  return b > 0xffffffffull ? 0xffffffffu : (uint32_t)b;
+}
+
 }  // namespace
 
 extern "C" {
@@ -251,7 +264,8 @@ int inet_server_step(inet_server *s, hipStream_t stream, uint32_t max_steps) {
   rc = kparams_for(cfg, nullptr, &kp);
   if (rc) return rc;
   rc = launch_reduce(s->rules, sh, grid, s->d_descs, s->d_order, n, s->d_counter, s->d_rules,
-                     max_steps, s->cfg.jump ? FLAG_JUMP : 0, kp, stream);
+                     round_budget(cfg, max_steps, n, grid), s->cfg.jump ? FLAG_JUMP : 0, kp,
+                     stream);
   if (rc) return rc;
   s->round_in_flight = true;
   return INET_OK;
@@ -568,7 +582,8 @@ int inet_server_run(inet_server *s, int32_t n_pool, const int32_t *label, const 
     KParams kp;
     if (!rc) rc = kparams_for(cfg, nullptr, &kp);
     if (!rc) rc = launch_reduce(R, sh, grid, s->d_descs, s->d_order, n, s->d_counter, s->d_rules,
-                                round_steps, s->cfg.jump ? FLAG_JUMP : 0, kp, stream);
+                                round_budget(cfg, round_steps, n, grid),
+                                s->cfg.jump ? FLAG_JUMP : 0, kp, stream);
     if (rc) break;
     if (hipMemcpyAsync(h_states, s->d_states, sizeof(NetState) * (size_t)M, hipMemcpyDeviceToHost,
                        stream) != hipSuccess) { rc = INET_EHIP; break; }
