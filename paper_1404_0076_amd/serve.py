@@ -132,14 +132,16 @@ def serve_native(rules, pool: Sequence, arrivals: np.ndarray, pick: Sequence[int
                  caps: Optional[Sequence] = None, max_slots: int = 4096,
                  workspace_bytes: int = 8 << 30, round_steps: int = 256, wg_size: int = 0,
                  time_limit: float = 600.0, server: Optional[Server] = None,
-                 per_rule: bool = False, want_nf=None) -> ServeReport:
+                 per_rule: bool = False, want_nf=None, **config) -> ServeReport:
     """The serving loop of ``serve`` run by the library (inet_server_run).
     Results carry counters; with ``per_rule`` also the per-rule counts, and
-    the normal forms of the requests flagged in ``want_nf``."""
+    the normal forms of the requests flagged in ``want_nf``.  ``config``:
+    further server configuration (``max_resident`` and the inet_config keys,
+    e.g. ``round_scale``)."""
     import torch
 
     srv = server or Server(rules, max_slots, workspace_bytes)
-    srv.set_config(wg_size=wg_size)
+    srv.set_config(wg_size=wg_size, **config)
     out = srv.run(pool, arrivals, pick, caps=caps, round_steps=round_steps,
                   time_limit=time_limit, stream=torch.cuda.current_stream(), per_rule=per_rule,
                   want_nf=want_nf)

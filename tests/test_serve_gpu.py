@@ -134,6 +134,33 @@ def test_native_loop_matches_oracle():
     srv.free()
 
 
+def test_native_loop_with_scaled_rounds():
+    # rounds whose budget grows with the running nets per engine (4 engines
+    # for up to 64 running nets): the same results, fewer rounds
+    pool = _pool()
+    refs = [oracle.reduce(R, n) for n in pool]
+    alone = [P.reduce_net(R, n)[0].steps for n in pool]
+    caps = [(n.n_agents + 4 * r.interactions + 1024, 4 * (n.n_agents + 4 * r.interactions + 1024))
+            for n, r in zip(pool, refs)]
+    rng = np.random.Generator(np.random.PCG64(12))
+    pick = rng.integers(0, len(pool), 600)
+    arrivals = np.zeros(len(pick))
+    rounds = {}
+    for scale in (0, 8):
+        srv = P.Server(R, 64, 1 << 30)
+        say("native serving, round scale", scale)
+        rep = serve_native(R, pool, arrivals, pick, caps=caps, round_steps=16, server=srv,
+                           max_resident=4, round_scale=scale)
+        assert len(rep.served) == len(pick)
+        for s in rep.served:
+            ref = refs[s.index]
+            assert s.status == ref.status and s.interactions == ref.interactions, s.index
+            assert s.steps == alone[s.index], s.index
+        rounds[scale] = rep.rounds
+        srv.free()
+    assert rounds[8] < rounds[0]
+
+
 def test_native_loop_retries_out_of_memory():
     pool = [n for _, n in small_exprs(12, 12, 5, 20_000, min_count=2_000)]
     refs = [oracle_run(R, n) for n in pool]
