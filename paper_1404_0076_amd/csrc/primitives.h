@@ -6,7 +6,8 @@
 // communication-eligible equations).  Each primitive is a few kernels over
 // tiles of 2048 elements (256 threads x 8 items) with a prefix sum over the
 // per-tile counts between them; temporary device memory comes from the
-// caller's Scratch.
+// caller's Scratch.  A single tile takes one launch per primitive (the
+// sort runs all its passes in LDS).
 #ifndef INET_PRIMITIVES_H
 #define INET_PRIMITIVES_H
 
@@ -160,6 +161,8 @@ __global__ __launch_bounds__(BLOCK) void k_flag_count(size_t n, F flag, uint32_t
 }
 
 // emit(i, position) for each flagged i; positions follow the input order
+// (cnt_incl / cnt: the tiles' inclusive and own counts, or null for a single
+// tile, which then also writes the total)
 template <class F, class E>
 __global__ __launch_bounds__(BLOCK) void k_flag_emit(size_t n, F flag, E emit,
                                                      const uint32_t *__restrict__ cnt_incl,
@@ -167,9 +170,12 @@ __global__ __launch_bounds__(BLOCK) void k_flag_emit(size_t n, F flag, E emit,
                                                      int64_t *__restrict__ n_out) {
   __shared__ uint32_t s_wave[WAVES];
   const size_t base = (size_t)blockIdx.x * TILE;
-  uint32_t off = cnt_incl[blockIdx.x] - cnt[blockIdx.x];
+  uint32_t off = cnt_incl ? cnt_incl[blockIdx.x] - cnt[blockIdx.x] : 0u;
   const int lane = __lane_id(), w = threadIdx.x >> 6;
-  for (int k = 0; k < ITEMS; k++) {
+  // rounds of BLOCK elements that hold any (the same in every thread)
+  const size_t left = n - base;
+  const int rounds = left >= (size_t)TILE ? ITEMS : (int)((left + BLOCK - 1) / BLOCK);
+  for (int k = 0; k < rounds; k++) {
     const size_t i = base + (size_t)k * BLOCK + threadIdx.x;
     const bool f = i < n && flag(i);
     const unsigned long long m = __ballot(f ? 1 : 0);
@@ -187,7 +193,8 @@ __global__ __launch_bounds__(BLOCK) void k_flag_emit(size_t n, F flag, E emit,
     off += all;
     __syncthreads();
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0 && n_out) *n_out = (int64_t)cnt_incl[blockIdx.x];
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0 && n_out)
+    *n_out = (int64_t)(cnt_incl ? cnt_incl[blockIdx.x] : off);
 }
 
 // runs flag/emit over [0, n); the number emitted lands in *d_n_out (device)
@@ -197,6 +204,11 @@ int compact(size_t n, F flag, E emit, int64_t *d_n_out, Scratch &S, hipStream_t 
     return hipMemsetAsync(d_n_out, 0, sizeof(int64_t), s) == hipSuccess ? 0 : -1;
   }
   const int t = tiles_of(n);
+  if (t == 1) {  // one tile: one launch, which also counts
+    hipLaunchKernelGGL((k_flag_emit<F, E>), dim3(1), dim3(BLOCK), 0, s, n, flag, emit,
+                       (const uint32_t *)nullptr, (const uint32_t *)nullptr, d_n_out);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  }
   uint32_t *cnt = nullptr, *incl = nullptr;
   if (S.take(4 * (size_t)t, (void **)&cnt) || S.take(4 * (size_t)t, (void **)&incl)) return -1;
   hipLaunchKernelGGL((k_flag_count<F>), dim3(t), dim3(BLOCK), 0, s, n, flag, cnt);
@@ -300,13 +312,82 @@ __global__ __launch_bounds__(BLOCK) void k_rs_scatter(const uint32_t *__restrict
   }
 }
 
+// one tile (n <= TILE) sorted by one block in LDS: the four passes of the
+// sort above (digit counts, their exclusive prefix, the stable scatter in
+// rounds of BLOCK elements) between two LDS buffers, one launch in all
+template <class V>
+__global__ __launch_bounds__(BLOCK) void k_rs_sort_tile(uint32_t *__restrict__ key,
+                                                        V *__restrict__ val, int n) {
+  __shared__ uint32_t sk[2][TILE];
+  __shared__ V sv[2][TILE];
+  __shared__ uint32_t run[RADIX], start[RADIX], s_wave[WAVES];
+  __shared__ uint32_t wcnt[WAVES][RADIX];
+  const int tid = threadIdx.x, w = tid >> 6;
+  for (int i = tid; i < n; i += BLOCK) {
+    sk[0][i] = key[i];
+    sv[0][i] = val[i];
+  }
+  for (int pass = 0; pass < 4; pass++) {
+    const int from = pass & 1, to = from ^ 1, shift = 8 * pass;
+    run[tid] = 0;
+    for (int q = 0; q < WAVES; q++) wcnt[q][tid] = 0;
+    __syncthreads();
+    for (int i = tid; i < n; i += BLOCK) atomicAdd(&run[(sk[from][i] >> shift) & 255u], 1u);
+    __syncthreads();
+    uint32_t tot;
+    const uint32_t c = run[tid];
+    start[tid] = block_excl_scan(c, s_wave, &tot);
+    run[tid] = 0;
+    __syncthreads();
+    for (int k = 0; k * BLOCK < n; k++) {  // the rounds that hold any element
+      const int i = k * BLOCK + tid;
+      const bool valid = i < n;
+      const uint32_t kk = valid ? sk[from][i] : 0u;
+      const uint32_t d = (kk >> shift) & 255u;
+      unsigned long long same = __ballot(valid ? 1 : 0);
+#pragma unroll
+      for (int b = 0; b < 8; b++) {
+        const unsigned long long m = __ballot(((d >> b) & 1u) ? 1 : 0);
+        same &= ((d >> b) & 1u) ? m : ~m;
+      }
+      const uint32_t rank = (uint32_t)__builtin_amdgcn_mbcnt_hi(
+          (unsigned)(same >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)same, 0u));
+      if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(same);
+      __syncthreads();
+      if (valid) {
+        uint32_t before = 0;
+        for (int q = 0; q < w; q++) before += wcnt[q][d];
+        const uint32_t p = start[d] + run[d] + before + rank;
+        sk[to][p] = kk;
+        sv[to][p] = sv[from][i];
+      }
+      __syncthreads();
+      uint32_t add = 0;
+      for (int q = 0; q < WAVES; q++) {
+        add += wcnt[q][tid];
+        wcnt[q][tid] = 0;
+      }
+      run[tid] += add;
+      __syncthreads();
+    }
+  }
+  for (int i = tid; i < n; i += BLOCK) {  // four passes: the result is in buffer 0
+    key[i] = sk[0][i];
+    val[i] = sv[0][i];
+  }
+}
+
 // sorts (key, val) by key, stably; the result is back in key / val (four
-// passes through key_alt / val_alt)
+// passes through key_alt / val_alt, or in LDS for one tile)
 template <class V>
 int radix_sort_pairs(uint32_t *key, V *val, uint32_t *key_alt, V *val_alt, size_t n, Scratch &S,
                      hipStream_t s) {
   if (n <= 1) return 0;
   const int t = tiles_of(n);
+  if (t == 1) {
+    hipLaunchKernelGGL((k_rs_sort_tile<V>), dim3(1), dim3(BLOCK), 0, s, key, val, (int)n);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  }
   uint32_t *hist = nullptr, *incl = nullptr;
   const size_t hn = (size_t)RADIX * t;
   if (S.take(4 * hn, (void **)&hist) || S.take(4 * hn, (void **)&incl)) return -1;
