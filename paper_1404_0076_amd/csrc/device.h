@@ -1061,12 +1061,13 @@ template <class F>
 __device__ __forceinline__ bool grid_sync(GridCtl *ctl, int G, int &seen, unsigned long long timeout,
                                           F &&last) {
   bool ok = true;
-  // every wave releases its own writes, and waits for the release, before
-  // the workgroup barrier (which does not wait for other waves' global stores)
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  // every wave's stores in the L2 before the workgroup barrier (which waits
+  // for LDS traffic only), then one agent-scope release by thread 0
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_s_waitcnt(0);
     if (gadd(&ctl->arrive, 1) == G - 1) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       last();
@@ -1617,15 +1618,15 @@ __device__ __forceinline__ void grid_body(const NetDesc *__restrict__ descs,
   int maxf = 0;  // widest frontier (workgroup 0, thread 0)
   for (;;) {
     // ---- post this workgroup's entry for the epoch, then read everyone's.
-    // Every wave releases its own writes of the epoch (records, cells, queue
-    // entries, the net's state) at agent scope before the workgroup barrier:
-    // the barrier does not wait for other waves' global stores, so a release
-    // by thread 0 alone could write back the cache before they arrive (the
-    // explicit wait makes each wave's release complete before the barrier).
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // Every wave waits until its own stores of the epoch (records, cells,
+    // queue entries, the net's state) have reached the L2 before the
+    // workgroup barrier, which waits for LDS traffic only; thread 0's
+    // agent-scope release then writes them all back before the entry.
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (tid == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __builtin_amdgcn_s_waitcnt(0);
       const bool err = mode == GM_GRID && S.status != 0;
       __hip_atomic_store(&ctl->ent[epoch & 1][me], ent_pack(epoch, err, count),
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
