@@ -236,7 +236,7 @@ def test_jump_in_batch_engines():
 @pytest.mark.parametrize("seed", range(5))
 @pytest.mark.parametrize("cfg", [{}, FORCED, TILE,
                                  dict(grid=16, grid_lo=2048, grid_hi=2048, grid_ppw=128, qcap=8192)],
-                         ids=["default", "forced", "tile", "tuned"])
+                         ids=["default", "forced", "tile", "g16-even"])
 def test_grid_config2_mul_full(seed, cfg):
     net = nets.config2_mul(seed)
     a, b = net.meta["a"], net.meta["b"]
@@ -245,6 +245,50 @@ def test_grid_config2_mul_full(seed, cfg):
             **cfg)
     assert g[0].interactions == mul_count(a, b)
     assert_same(g, oracle_run(R, net), f"grid config2 seed {seed}")
+
+
+@pytest.mark.slow
+def test_grid_hand_offs_see_every_wave_s_stores():
+    # regression: with 16 workgroups and equal hand-off thresholds, Mul hands
+    # the net between workgroup 0 and the shared steps hundreds of times; once every wave's stores of an
+    # epoch were not waited for before the workgroup barrier, a hand-off
+    # could read queue entries another workgroup had not yet made visible
+    net = nets.config2_mul(0)
+    a, b = net.meta["a"], net.meta["b"]
+    h = P.load(R, net, agent_cap=a * b + 4 * (a + b) + 4096, name_cap=4 * a * b + 8 * (a + b) + 4096)
+    h.set_config(grid=16, grid_lo=2048, grid_hi=2048, grid_ppw=128, qcap=8192)
+    for k in range(8):
+        h.reset()
+        res = h.reduce()[0]
+        say("hand-offs", k, res.status, res.interactions)
+        assert res.status == P.OK and res.n_stuck == 0 and res.interactions == mul_count(a, b)
+    h.free()
+
+
+# the single-net workloads at full size, each in the launch shape the
+# benchmark takes from the tuned table on this device
+TUNED_SINGLES = {
+    "addtree": lambda: (R, nets.config1_add_tree(0)),
+    "mul": lambda: (R, nets.config2_mul(0)),
+    "fib27": lambda: (R, nets.config3_fib(27)),
+    "algae27": lambda: (nets.algae_rules(), nets.algae_net(27)),
+    "ackermann": lambda: (nets.ackermann_rules(), nets.ackermann_net(3, 7)),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("which", list(TUNED_SINGLES))
+def test_tuned_single_net_shapes(which):
+    from paper_1404_0076_amd import autotune
+    rules, net = TUNED_SINGLES[which]()
+    best = autotune.lookup([net], autotune.SINGLE_SPACE)
+    if best is None:
+        pytest.skip("no tuned entry for this device")
+    cfg = dict(best["config"])
+    wg = cfg.pop("wg_size", 1024) or 1024
+    say("tuned single", which, wg, cfg)
+    g = gpu(rules, net, wg_size=wg, agent_cap=1 << 25, name_cap=1 << 26, **cfg)
+    assert_same(g, oracle_run(rules, net), f"tuned single {which}")
 
 
 @pytest.mark.slow
@@ -262,14 +306,14 @@ def test_grid_fib27_and_add_tree(cfg):
     assert_same(g, oracle_run(R, net), "grid add tree")
 
 
-# the benchmark's tuned shape: 64 workgroups of 512 lanes, full chunks, so
-# the heap reservation is taken once per workgroup
-ALGAE_TUNED = dict(wg_size=512, grid=64, grid_lo=256, grid_hi=1024, grid_ppw=256, qcap=8192)
+# 64 workgroups of 512 lanes, full chunks, so the heap reservation is taken
+# once per workgroup
+ALGAE_512 = dict(wg_size=512, grid=64, grid_lo=256, grid_hi=1024, grid_ppw=256, qcap=8192)
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("cfg", [{}, FORCED, ONE_WG, TILE, ALGAE_TUNED],
-                         ids=["default", "forced", "one", "tile", "tuned"])
+@pytest.mark.parametrize("cfg", [{}, FORCED, ONE_WG, TILE, ALGAE_512],
+                         ids=["default", "forced", "one", "tile", "wg512"])
 def test_grid_algae_27(cfg):
     rules = nets.algae_rules()
     net = nets.algae_net(27)
