@@ -381,8 +381,9 @@ def main():
         print(kernel_sources_hash())
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(nets are independent; see DESIGN.md for how the batch would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path (the nets of a "
+              "batch are independent, so each GPU would reduce its own share of them)",
+              file=sys.stderr)
         sys.exit(2)
 
     par_baseline = None
