@@ -333,10 +333,10 @@ def test_config3_fib_full(n):
 
 @pytest.mark.slow
 def test_config4_batch_full():
-    """The 4096-net batch (seed 0) in the launch configuration the benchmark
-    times: 1024-lane engines, one resident engine per compute unit, longest
-    critical path first, heaps sized exactly; every net against the oracle,
-    eagerly and by HIP-graph replay."""
+    """The 4096-net batch (seed 0): 1024-lane engines, one resident engine per
+    compute unit, longest critical path first, heaps sized exactly, eagerly
+    and by HIP-graph replay; then in the launch configuration the benchmark
+    times (the tuned shape); every net against the oracle."""
     import torch
     batch = nets.config4_batch(seed=0)
     say("config4 oracle", len(batch))
@@ -372,4 +372,18 @@ def test_config4_batch_full():
         rs = h.results()
         for i in range(len(batch)):
             assert_same((rs[i], h.readback(i), h.per_rule(i)), refs[i], f"graph {rep} net {i}")
+    h.free()
+    # the shape the benchmark takes from the tuned table on this device
+    from paper_1404_0076_amd import autotune
+    best = autotune.lookup(batch, autotune.BATCH_SPACE)
+    if best is None:
+        say("config4: no tuned entry for this device")
+        return
+    say("config4 tuned shape", best["config"])
+    h = P.batch_load(R, batch, agent_caps=used_a + 64, name_caps=used_n + 64)
+    h.set_config(**best["config"])
+    h.set_order(np.argsort(-steps, kind="stable").astype(np.int32))
+    rs = h.reduce()
+    for i in range(len(batch)):
+        assert_same((rs[i], h.readback(i), h.per_rule(i)), refs[i], f"tuned shape net {i}")
     h.free()
