@@ -1259,6 +1259,12 @@ __device__ __forceinline__ void engine_net(EngineLds<QCAP> &S, const NetDesc &D,
       C.next = 0;
       int n = __builtin_amdgcn_readfirstlane(S.cnt[ci]);  // pairs in the frontier q[cur]
       int maxf = __builtin_amdgcn_readfirstlane(S.maxf);
+      // the step count and budget are wave-uniform (they come from global
+      // loads, which the compiler cannot see as uniform): in scalar registers
+      // the loop's exit is a scalar branch and the loop needs no exec-mask
+      // bookkeeping, and every value carried round it stays scalar too
+      steps = __builtin_amdgcn_readfirstlane(steps);
+      const unsigned stop_w = __builtin_amdgcn_readfirstlane(stop);
       int ha = -1, hb_ = 0;  // the lane's held pair (ha < 0: none)
       int nh = 0;            // held pairs of the wave
       // the held pairs back into the frontier, after its n pairs
@@ -1280,7 +1286,7 @@ __device__ __forceinline__ void engine_net(EngineLds<QCAP> &S, const NetDesc &D,
       };
       for (;;) {
         const int tot = n + nh;
-        if (!(tot > 0 && tot <= limit && C.err >= 0 && steps < stop)) break;
+        if (!(tot > 0 && tot <= limit && C.err >= 0 && steps < stop_w)) break;
         if (tot > maxf) maxf = tot;
         if constexpr (NARROW)
           if ((steps & 1023u) == 0 && __lane_id() == 0) gstore(hb, (int)steps);
