@@ -1369,7 +1369,11 @@ __device__ __forceinline__ void engine_net(EngineLds<QCAP> &S, const NetDesc &D,
       for (;;) {
         __syncthreads();
         const int n = S.cnt[ci];
-        if (n == 0 || S.status < 0 || steps >= stop || (NARROW && n > hi)) break;
+        const int status = S.status;
+        // every wave holds the step's control words before any wave can write
+        // the status again (an error found in the step), so all decide alike
+        __syncthreads();
+        if (n == 0 || status < 0 || steps >= stop || (NARROW && n > hi)) break;
         if (!LANE && n <= solo_max) {
           if (tid < 64) {
             if (!NARROW || hi >= SOLO_MAX) solo(SOLO_MAX);
@@ -1418,7 +1422,9 @@ __device__ __forceinline__ void engine_net(EngineLds<QCAP> &S, const NetDesc &D,
   for (;;) {
     __syncthreads();
     const int n = S.cnt[ci];
-    if (n == 0 || S.status < 0 || steps >= stop || (NARROW && n > hi)) break;
+    const int status = S.status;
+    __syncthreads();  // as above: all waves read before any can write the status
+    if (n == 0 || status < 0 || steps >= stop || (NARROW && n > hi)) break;
     const int cn = ci == 2 ? 0 : ci + 1;
     const int cnn = cn == 2 ? 0 : cn + 1;
     if (tid == 0) {
