@@ -271,6 +271,27 @@ def test_out_of_memory_reported(engine):
     h.free()
 
 
+def test_out_of_memory_in_a_wide_step_leaves_the_engine_usable():
+    """An error found in a step that all waves of a 1024-lane engine share
+    (the Add tree's first steps hold about 1,000 pairs, each making a fresh
+    name cell, against a name heap 16 cells larger than the net) ends that
+    net with ENOMEM; the one resident engine then takes the next nets, which
+    must still match the oracle (every wave left the error step alike)."""
+    wide = nets.config1_add_tree(0)
+    others = [nets.mul_net(30, 41), nets.fib_net(12), nets.config1_add_tree(3, 64, 30)]
+    refs = [oracle_run(R, n) for n in others]
+    caps = [max(4 * n.n_agents + 4096, 1 << 16) for n in [wide] + others]
+    ncaps = [wide.n_names + 16] + [4 * c for c in caps[1:]]
+    h = P.batch_load(R, [wide] + others, agent_caps=caps, name_caps=ncaps)
+    h.set_config(wg_size=1024, max_resident=1)
+    rs = h.reduce()
+    say("wide step out of memory", rs[0].status, rs[0].steps, rs[0].max_frontier)
+    assert rs[0].status == P.ENOMEM and rs[0].max_frontier > 64
+    for i, ref in enumerate(refs, 1):
+        assert_same((rs[i], h.readback(i), h.per_rule(i)), ref, f"net {i} after the error")
+    h.free()
+
+
 def test_reset_repeats_exactly():
     net = MID
     ref = oracle_run(R, net)
