@@ -24,8 +24,10 @@
 //           equation between two agents is a new active pair;
 //   compaction -- new active pairs are appended to the next frontier with a
 //           wave ballot, a mask prefix count and one counter update per wave.
-// Engines of several waves separate steps with one workgroup barrier; a
-// single wave needs none (its memory operations are ordered).  After the
+// Engines of several waves separate steps with workgroup barriers (two per
+// step: one after the step's writes, one after every wave has read the next
+// step's control words); a single wave needs none (its memory operations are
+// ordered).  After the
 // loop, name-to-name chains left in the cells (the partial com of the remark
 // after the correctness proposition of Section 3.6) are compressed by pointer
 // jumping.
