@@ -11,7 +11,7 @@ import ctypes
 import dataclasses
 import os
 import subprocess
-from typing import List, Optional
+from typing import Optional
 
 import numpy as np
 

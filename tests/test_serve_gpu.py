@@ -1,7 +1,6 @@
 """GPU: hipGraph replay of a batched step, and continuous batching -- every
 served result equals the oracle's and the result of the same net reduced
 alone, whatever else was resident."""
-import sys
 
 import numpy as np
 import pytest
